@@ -1,0 +1,284 @@
+/*
+ * Seam-carving ORACLE -- plain, slow, obviously correct CPU reference.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file: only tests/, __graft_entry__.smoke() and bench.py's
+ * cpu_baseline leg use it.  It shares no code, header, table or helper with
+ * the HIP library; the two meet only at the seeded input bytes.
+ *
+ * Paper: "Analysis of Different Algorithmic Design Techniques for Seam
+ * Carving" (arXiv 2410.21207).  Every function cites the passage it follows.
+ * All arithmetic is integer (the paper fixes no precision; the energy of a
+ * uint8 image is a sum of byte differences), so there is no rounding anywhere
+ * and the GPU path must agree bit for bit.
+ *
+ * Readings of passages the paper leaves open (each is listed in the design doc):
+ *   R1  e1 energy (sec. "Energy Mapping", the e1 bullet): the x and y partial
+ *       derivatives are central differences without the 1/2 factor,
+ *       |I(y,x+1)-I(y,x-1)| + |I(y+1,x)-I(y-1,x)|, summed over all C channels.
+ *   R2  image border: indices are clamped to the image (clamp-to-edge), so a
+ *       border pixel uses a one-sided difference; W==1 or H==1 makes that
+ *       term zero.
+ *   R3  first DP row (Alg. 3 never initialises it): M(0,j) = e(0,j).
+ *   R4  DP edges (Alg. 3 reads M[i-1,j-1] at j=1 and M[i-1,j+1] at j=m):
+ *       out-of-range parents are excluded, not clamped.
+ *   R5  parent tie-break (Alg. 3: idx = argmin over (j-1, j, j+1), B = idx+j-1):
+ *       the FIRST minimum in left-to-right order, i.e. the leftmost parent.
+ *   R6  last-row argmin (Alg. 3, "argmin M(n,:)"): the leftmost minimum.
+ *   R7  backtrack (Alg. 3 appends B[k,j] for k=n..1 and never the start
+ *       column): s[H-1] = j*, s[i-1] = parent of (i, s[i]); 0-based rows.
+ *   R8  removal (sec. "Removal of Seams"): pixels right of the seam shift
+ *       left by one column, nothing is blended; the width drops by one.
+ *   R9  carve driver (flowchart, and the cost C(n,m,s') of the brute-force
+ *       section): each seam is the minimum seam of the CURRENT image, with
+ *       the energy recomputed after every removal.
+ *   R10 horizontal seams (sec. "Design Techniques", reduction by swapping
+ *       rows and columns): a plain transpose, vertical seams first.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define SCO_OK 0
+#define SCO_EINVAL (-1)
+#define SCO_ENOMEM (-2)
+#define SCO_ETOOBIG (-3)
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+static int absi(int v) { return v < 0 ? -v : v; }
+
+/*
+ * e1 energy, sec. "Energy Mapping" (first bullet), with readings R1, R2.
+ * img: H rows of `pitch` bytes, pixel (y,x) channel c at img[y*pitch + x*C + c].
+ * e:   H*W int32, dense, e[y*W + x].
+ */
+int sco_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t* e) {
+    if (!img || !e || H < 1 || W < 1 || C < 1 || pitch < W * C) return SCO_EINVAL;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            int xl = clampi(x - 1, 0, W - 1), xr = clampi(x + 1, 0, W - 1);
+            int yu = clampi(y - 1, 0, H - 1), yd = clampi(y + 1, 0, H - 1);
+            int32_t s = 0;
+            for (int c = 0; c < C; ++c) {
+                int dx = (int)img[(size_t)y * pitch + (size_t)xr * C + c] -
+                         (int)img[(size_t)y * pitch + (size_t)xl * C + c];
+                int dy = (int)img[(size_t)yd * pitch + (size_t)x * C + c] -
+                         (int)img[(size_t)yu * pitch + (size_t)x * C + c];
+                s += absi(dx) + absi(dy);
+            }
+            e[(size_t)y * W + x] = s;
+        }
+    }
+    return SCO_OK;
+}
+
+/*
+ * Minimum vertical seam by dynamic programming: the recurrence
+ * M(i,j) = e(i,j) + min(M(i-1,j-1), M(i-1,j), M(i-1,j+1)) of the DP section,
+ * filled as in Alg. 3, then the bottom-row argmin and the backtrack, with
+ * readings R3-R7.
+ *
+ * e: H*W int32 (any values; the sums are formed in int64).
+ * M: nullable, H*W int64, receives the whole cumulative table.
+ * D: nullable, H*W uint8, receives the parent direction best-j+1 in {0,1,2}
+ *    (0 = upper-left, 1 = straight up, 2 = upper-right); row 0 has no parent
+ *    and is set to 1.
+ * seam: H int32, seam[i] = column of the seam in row i (top to bottom).
+ * cost: the seam's total energy, M(H-1, seam[H-1]).
+ */
+int sco_dp(const int32_t* e, int H, int W, int64_t* M, uint8_t* D, int32_t* seam, int64_t* cost) {
+    if (!e || !seam || !cost || H < 1 || W < 1) return SCO_EINVAL;
+    int64_t* m = M ? M : (int64_t*)malloc(sizeof(int64_t) * (size_t)H * W);
+    uint8_t* d = D ? D : (uint8_t*)malloc((size_t)H * W);
+    if (!m || !d) {
+        if (!M) free(m);
+        if (!D) free(d);
+        return SCO_ENOMEM;
+    }
+    for (int j = 0; j < W; ++j) {           /* R3 */
+        m[j] = e[j];
+        d[j] = 1;
+    }
+    for (int i = 1; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            int best = -1;
+            for (int p = j - 1; p <= j + 1; ++p) {      /* scanned left to right (R5) */
+                if (p < 0 || p >= W) continue;          /* R4 */
+                if (best < 0 || m[(size_t)(i - 1) * W + p] < m[(size_t)(i - 1) * W + best]) best = p;
+            }
+            m[(size_t)i * W + j] = (int64_t)e[(size_t)i * W + j] + m[(size_t)(i - 1) * W + best];
+            d[(size_t)i * W + j] = (uint8_t)(best - j + 1);
+        }
+    }
+    int jstar = 0;                                       /* R6 */
+    for (int j = 1; j < W; ++j)
+        if (m[(size_t)(H - 1) * W + j] < m[(size_t)(H - 1) * W + jstar]) jstar = j;
+    *cost = m[(size_t)(H - 1) * W + jstar];
+    seam[H - 1] = jstar;                                 /* R7 */
+    for (int i = H - 1; i >= 1; --i) seam[i - 1] = seam[i] + (int)d[(size_t)i * W + seam[i]] - 1;
+    if (!M) free(m);
+    if (!D) free(d);
+    return SCO_OK;
+}
+
+/*
+ * Seam removal, sec. "Removal of Seams" (R8): in row i every pixel right of
+ * column seam[i] moves one column left.  In place at unchanged pitch; the
+ * bytes of the old last column (W-1) are left as they were.
+ */
+int sco_remove_seam(uint8_t* img, int H, int W, int C, int pitch, const int32_t* seam) {
+    if (!img || !seam || H < 1 || W < 1 || C < 1 || pitch < W * C) return SCO_EINVAL;
+    for (int i = 0; i < H; ++i)
+        if (seam[i] < 0 || seam[i] >= W) return SCO_EINVAL;
+    for (int i = 0; i < H; ++i) {
+        uint8_t* row = img + (size_t)i * pitch;
+        for (int x = seam[i]; x < W - 1; ++x)
+            for (int c = 0; c < C; ++c) row[(size_t)x * C + c] = row[(size_t)(x + 1) * C + c];
+    }
+    return SCO_OK;
+}
+
+/*
+ * Carve driver (R9): remove W - target_w vertical seams one at a time, each
+ * the minimum seam of the current image with its energy fully recomputed.
+ * seams_out: nullable, (W-target_w)*H int32, seam k at seams_out[k*H + i],
+ *            in the column coordinates of the image it was removed from.
+ * costs_out: nullable, (W-target_w) int64.
+ * The result occupies the first target_w*C bytes of each row.
+ */
+int sco_carve(uint8_t* img, int H, int W, int C, int pitch, int target_w, int32_t* seams_out,
+              int64_t* costs_out) {
+    if (!img || H < 1 || W < 1 || C < 1 || pitch < W * C || target_w < 1 || target_w > W) return SCO_EINVAL;
+    int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (size_t)H * W);
+    int32_t* s = (int32_t*)malloc(sizeof(int32_t) * (size_t)H);
+    if (!e || !s) {
+        free(e);
+        free(s);
+        return SCO_ENOMEM;
+    }
+    int rc = SCO_OK;
+    for (int k = 0, w = W; w > target_w; ++k, --w) {
+        int64_t cost = 0;
+        if ((rc = sco_energy(img, H, w, C, pitch, e)) != SCO_OK) break;
+        if ((rc = sco_dp(e, H, w, NULL, NULL, s, &cost)) != SCO_OK) break;
+        if ((rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;
+        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);
+        if (costs_out) costs_out[k] = cost;
+    }
+    free(e);
+    free(s);
+    return rc;
+}
+
+/* Plain transpose J(x,y,c) = I(y,x,c) (R10).  dst has W rows of dpitch bytes. */
+int sco_transpose(const uint8_t* src, int H, int W, int C, int spitch, uint8_t* dst, int dpitch) {
+    if (!src || !dst || H < 1 || W < 1 || C < 1 || spitch < W * C || dpitch < H * C) return SCO_EINVAL;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int c = 0; c < C; ++c)
+                dst[(size_t)x * dpitch + (size_t)y * C + c] = src[(size_t)y * spitch + (size_t)x * C + c];
+    return SCO_OK;
+}
+
+/*
+ * Two-direction carve (R10): remove W-target_w vertical seams from img in
+ * place, then transpose, remove H-target_h vertical seams of the transposed
+ * image (the horizontal seams of the original) and transpose back into out
+ * (target_h rows of out_pitch bytes).  Seam logs are optional:
+ * vseams (W-target_w)*H, hseams (H-target_h)*target_w.
+ */
+int sco_carve_hv(uint8_t* img, int H, int W, int C, int pitch, int target_w, int target_h, uint8_t* out,
+                 int out_pitch, int32_t* vseams, int64_t* vcosts, int32_t* hseams, int64_t* hcosts) {
+    if (!img || !out || H < 1 || W < 1 || C < 1 || pitch < W * C || target_w < 1 || target_w > W ||
+        target_h < 1 || target_h > H || out_pitch < target_w * C)
+        return SCO_EINVAL;
+    int rc = sco_carve(img, H, W, C, pitch, target_w, vseams, vcosts);
+    if (rc != SCO_OK) return rc;
+    int tp = H * C; /* transposed image: target_w rows of H pixels */
+    uint8_t* t = (uint8_t*)malloc((size_t)target_w * tp);
+    if (!t) return SCO_ENOMEM;
+    rc = sco_transpose(img, H, target_w, C, pitch, t, tp);
+    if (rc == SCO_OK) rc = sco_carve(t, target_w, H, C, tp, target_h, hseams, hcosts);
+    if (rc == SCO_OK) rc = sco_transpose(t, target_w, target_h, C, tp, out, out_pitch);
+    free(t);
+    return rc;
+}
+
+/*
+ * Greedy seam, Alg. 2: start at the leftmost minimum of the bottom row of E,
+ * then climb choosing the leftmost minimal in-range neighbour among
+ * (j-1, j, j+1) of the row above; the cost is the sum of E on the path.
+ */
+int sco_greedy_seam(const int32_t* e, int H, int W, int32_t* seam, int64_t* cost) {
+    if (!e || !seam || !cost || H < 1 || W < 1) return SCO_EINVAL;
+    int start = 0;
+    for (int j = 1; j < W; ++j)
+        if (e[(size_t)(H - 1) * W + j] < e[(size_t)(H - 1) * W + start]) start = j;
+    int64_t c = e[(size_t)(H - 1) * W + start];
+    seam[H - 1] = start;
+    for (int i = H - 2; i >= 0; --i) {
+        int best = -1;
+        for (int p = start - 1; p <= start + 1; ++p) {
+            if (p < 0 || p >= W) continue;
+            if (best < 0 || e[(size_t)i * W + p] < e[(size_t)i * W + best]) best = p;
+        }
+        start = best;
+        seam[i] = start;
+        c += e[(size_t)i * W + start];
+    }
+    *cost = c;
+    return SCO_OK;
+}
+
+/*
+ * Brute-force seam, Alg. 1: enumerate every connected top-to-bottom path
+ * (each step moves at most one column, sec. "Seam Identification"), keep the
+ * cheapest.  Paths are generated from the bottom row upward, start columns in
+ * ascending order and, at each row, the candidate columns (j-1, j, j+1) in
+ * ascending order; with the strict "<" of Alg. 1 the first cheapest path in
+ * this order wins, i.e. the minimum of the key (cost, s[H-1], s[H-2], ..., s[0]).
+ * Refuses inputs with more than ~5e7 paths.
+ */
+struct bf_ctx {
+    const int32_t* e;
+    int H, W;
+    int32_t* cur;
+    int32_t* best;
+    int64_t best_cost;
+    int have;
+};
+
+static void bf_rec(struct bf_ctx* c, int row, int col, int64_t acc) {
+    acc += c->e[(size_t)row * c->W + col];
+    c->cur[row] = col;
+    if (row == 0) {
+        if (!c->have || acc < c->best_cost) {
+            c->have = 1;
+            c->best_cost = acc;
+            memcpy(c->best, c->cur, sizeof(int32_t) * (size_t)c->H);
+        }
+        return;
+    }
+    for (int p = col - 1; p <= col + 1; ++p)
+        if (p >= 0 && p < c->W) bf_rec(c, row - 1, p, acc);
+}
+
+int sco_brute_seam(const int32_t* e, int H, int W, int32_t* seam, int64_t* cost) {
+    if (!e || !seam || !cost || H < 1 || W < 1) return SCO_EINVAL;
+    double paths = W;
+    for (int i = 1; i < H; ++i) paths *= 3.0;
+    if (paths > 5e7) return SCO_ETOOBIG;
+    struct bf_ctx c;
+    c.e = e;
+    c.H = H;
+    c.W = W;
+    c.cur = (int32_t*)malloc(sizeof(int32_t) * (size_t)H);
+    c.best = seam;
+    c.best_cost = 0;
+    c.have = 0;
+    if (!c.cur) return SCO_ENOMEM;
+    for (int j = 0; j < W; ++j) bf_rec(&c, H - 1, j, 0);
+    free(c.cur);
+    *cost = c.best_cost;
+    return SCO_OK;
+}

@@ -1,0 +1,258 @@
+"""Pins of the oracle: checks against what the paper and the mathematics fix.
+
+Every check takes an ``oracle.Oracle`` instance so that ``test_oracle_mutants``
+can run the same pins against deliberately broken builds of the oracle and show
+that each plausible mistake fails at least one of them.  None of these checks
+retypes the oracle's formulas: they use hand-worked values, brute-force
+enumeration of all seams (the definition of the minimum seam, Alg. 1), closed
+forms and invariants of the method.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def py_brute_seam(E):
+    """Enumerate every connected top-to-bottom seam (sec. 'Seam Identification':
+    a path moving at most one column per row) and return the minimum of the key
+    (cost, s[H-1], s[H-2], ..., s[0]): the cheapest seam, ties resolved by the
+    leftmost column at the bottom, then the leftmost one row up, and so on.
+    Pure Python; tiny maps only."""
+    E = np.asarray(E)
+    H, W = E.shape
+    best = None
+    for start in range(W):
+        for moves in itertools.product((-1, 0, 1), repeat=H - 1):
+            path = [start]
+            ok = True
+            for mv in moves:
+                c = path[-1] + mv
+                if c < 0 or c >= W:
+                    ok = False
+                    break
+                path.append(c)
+            if not ok:
+                continue
+            cost = int(sum(int(E[H - 1 - t, path[t]]) for t in range(H)))
+            key = (cost, tuple(path))
+            if best is None or key < best:
+                best = key
+    cost, path = best
+    return np.array(path[::-1], np.int32), cost
+
+
+def tiny_cases(n, seed):
+    """Random tiny energy maps, many with tie-heavy alphabets."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n):
+        H = int(rng.integers(1, 7))
+        W = int(rng.integers(1, 7))
+        alpha = [2, 3, 4, 10, 1000][t % 5]
+        out.append(rng.integers(0, alpha, size=(H, W)).astype(np.int32))
+    return out
+
+
+def check_seam_valid(seam, H, w):
+    assert seam.shape == (H,)
+    assert np.all(seam >= 0) and np.all(seam < w), "seam leaves the image"
+    if H > 1:
+        assert np.all(np.abs(np.diff(seam.astype(np.int64))) <= 1), "seam not 8-connected"
+
+
+# ---------------------------------------------------------------- hand-worked
+def pin_hand_grids(o):
+    g = load_golden("hand_grids.json")
+    for case in g["energy_grids"]:
+        E = np.array(case["E"], np.int32)
+        seam, cost, M, D = o.dp_seam(E, full=True)
+        assert M.tolist() == case["M"], case["name"]
+        assert seam.tolist() == case["seam"], case["name"]
+        assert cost == case["cost"], case["name"]
+        gs, gc = o.greedy_seam(E)
+        assert gs.tolist() == case["greedy_seam"], case["name"]
+        assert gc == case["greedy_cost"], case["name"]
+        bs, bc = o.brute_seam(E)
+        assert bs.tolist() == case["seam"] and bc == case["cost"], case["name"]
+
+
+def pin_pixel_grid(o):
+    g = load_golden("hand_grids.json")
+    for case in g["pixel_grids"]:
+        grey = np.array(case["grey"], np.uint8)
+        img = np.repeat(grey[:, :, None], case["channels"], axis=2)
+        e = o.energy(img)
+        assert e.tolist() == case["energy"], case["name"]
+        seam, cost, M, _ = o.dp_seam(e, full=True)
+        assert M.tolist() == case["M"], case["name"]
+        assert seam.tolist() == case["seam"] and cost == case["cost"], case["name"]
+        out = o.remove_seam(img, seam)
+        assert out[:, :, 0].tolist() == case["grey_after_one_seam"], case["name"]
+        assert np.all(out == out[:, :, :1]), case["name"]
+        assert o.energy(out).tolist() == case["energy_after_one_seam"], case["name"]
+        out2, seams, costs = o.carve(img, img.shape[1] - 1)
+        assert np.array_equal(out2, out) and seams[0].tolist() == case["seam"] and costs[0] == case["cost"]
+
+
+# --------------------------------------------------------------- brute force
+def pin_bruteforce(o, n=300, seed=11):
+    for E in tiny_cases(n, seed):
+        ps, pc = py_brute_seam(E)
+        seam, cost = o.dp_seam(E)
+        assert seam.tolist() == ps.tolist() and cost == pc, (E.tolist(), seam, ps)
+        bs, bc = o.brute_seam(E)
+        assert bs.tolist() == ps.tolist() and bc == pc, (E.tolist(), bs, ps)
+
+
+def pin_bruteforce_large(o, sizes=((12, 12), (10, 12), (12, 9), (8, 11)), seed=12):
+    """DP == exhaustive enumeration up to the paper's largest brute-force size (12x12)."""
+    rng = np.random.default_rng(seed)
+    for (H, W) in sizes:
+        for alpha in (3, 50, 2000):
+            E = rng.integers(0, alpha, size=(H, W)).astype(np.int32)
+            assert _same(o.dp_seam(E), o.brute_seam(E)), (H, W, alpha)
+
+
+def _same(a, b):
+    return a[0].tolist() == b[0].tolist() and a[1] == b[1]
+
+
+# -------------------------------------------------------------- closed forms
+def pin_energy_closed_forms(o):
+    rng = np.random.default_rng(5)
+    # constant image: zero energy
+    for (H, W, C) in [(1, 1, 3), (5, 7, 3), (4, 1, 1), (1, 6, 4)]:
+        img = np.full((H, W, C), int(rng.integers(0, 256)), np.uint8)
+        assert np.all(o.energy(img) == 0)
+    # horizontal ramp I(y,x,c) = x: central difference 2 inside, one-sided 1 at the clamped edges
+    for (H, W, C) in [(3, 2, 3), (4, 9, 3), (2, 5, 1), (1, 3, 4)]:
+        img = np.broadcast_to(np.arange(W, dtype=np.uint8)[None, :, None], (H, W, C)).copy()
+        row = [C * (1 if (x == 0 or x == W - 1) else 2) for x in range(W)]
+        if W == 1:
+            row = [0]
+        assert o.energy(img).tolist() == [row] * H
+    # vertical ramp I(y,x,c) = 3y
+    H, W, C = 6, 4, 2
+    img = np.broadcast_to((3 * np.arange(H, dtype=np.uint8))[:, None, None], (H, W, C)).copy()
+    col = [C * 3 * (1 if (y == 0 or y == H - 1) else 2) for y in range(H)]
+    assert o.energy(img).tolist() == [[v] * W for v in col]
+    # anti-diagonal ramp I = 50 + 5x - 5y: the x and y differences have opposite signs, the energy
+    # adds their magnitudes: 10 per axis inside, 5 per axis at a clamped edge
+    H, W, C = 5, 6, 3
+    yy, xx = np.mgrid[0:H, 0:W]
+    img = np.repeat((50 + 5 * xx - 5 * yy).astype(np.uint8)[:, :, None], C, axis=2)
+    ax = lambda n, i: 5 if (i == 0 or i == n - 1) else 10  # noqa: E731
+    assert o.energy(img).tolist() == [[C * (ax(W, x) + ax(H, y)) for x in range(W)] for y in range(H)]
+    # a single bright pixel (value v) in channel 1 of a zero image, at an interior point and a corner
+    H, W, C, v = 5, 6, 3, 200
+    img = np.zeros((H, W, C), np.uint8)
+    img[2, 3, 1] = v
+    exp = np.zeros((H, W), np.int64)
+    exp[2, 2] = exp[2, 4] = exp[1, 3] = exp[3, 3] = v
+    assert np.array_equal(o.energy(img), exp)
+    img = np.zeros((H, W, C), np.uint8)
+    img[0, 0, 2] = v
+    exp = np.zeros((H, W), np.int64)
+    exp[0, 0] = 2 * v      # both one-sided differences at the corner see the pixel itself
+    exp[0, 1] = v          # central x-difference at (0,1) reaches back to (0,0)
+    exp[1, 0] = v          # central y-difference at (1,0) reaches up to (0,0)
+    assert np.array_equal(o.energy(img), exp)
+
+
+def pin_energy_symmetry(o):
+    """The e1 stencil treats x and y alike: energy(I^T) == energy(I)^T."""
+    rng = np.random.default_rng(6)
+    for (H, W, C) in [(7, 11, 3), (1, 9, 3), (13, 2, 4), (16, 16, 1)]:
+        img = rng.integers(0, 256, size=(H, W, C), dtype=np.uint8)
+        assert np.array_equal(o.energy(o.transpose(img)), o.energy(img).T)
+        assert np.array_equal(o.transpose(img), np.transpose(img, (1, 0, 2)))
+
+
+def pin_carve_closed_forms(o):
+    # constant image: every seam is column 0 with cost 0; the output is the left part
+    img = np.full((6, 9, 3), 77, np.uint8)
+    out, seams, costs = o.carve(img, 4)
+    assert np.all(seams == 0) and np.all(costs == 0) and np.array_equal(out, img[:, :4])
+    # horizontal ramp I = x: energy row [3,6,...,6,3]; column 0 ties with the last column, leftmost wins,
+    # the remaining image is again a ramp, so every seam is column 0 with cost 3H and the output is I[:, k:]
+    H, W = 5, 12
+    img = np.broadcast_to(np.arange(W, dtype=np.uint8)[None, :, None], (H, W, 3)).copy()
+    out, seams, costs = o.carve(img, 7)
+    assert np.all(seams == 0) and np.all(costs == 3 * H) and np.array_equal(out, img[:, 5:])
+    # H == 1: the seam is the leftmost argmin of the single energy row
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        img = rng.integers(0, 4, size=(1, 8, 3), dtype=np.uint8)
+        e = o.energy(img)
+        seam, cost = o.dp_seam(e)
+        assert seam[0] == int(np.argmin(e[0])) and cost == int(e[0].min())
+    # target_w == W is the identity
+    img = rng.integers(0, 256, size=(4, 5, 3), dtype=np.uint8)
+    out, seams, costs = o.carve(img, 5)
+    assert np.array_equal(out, img) and seams.shape == (0, 4)
+
+
+# ---------------------------------------------------------------- invariants
+def carve_invariants(o, img, target_w, check_brute=False):
+    """Run the carve seam by seam and check every invariant of the method on each seam."""
+    out, seams, costs = o.carve(img, target_w)
+    cur = img.copy()
+    H = img.shape[0]
+    for k in range(seams.shape[0]):
+        w = cur.shape[1]
+        e = o.energy(cur)
+        s = seams[k]
+        check_seam_valid(s, H, w)
+        assert costs[k] == int(e[np.arange(H), s].sum()), "cost != sum of energy on the seam"
+        assert (s.tolist(), int(costs[k])) == (lambda r: (r[0].tolist(), r[1]))(o.dp_seam(e))
+        _, gc = o.greedy_seam(e)
+        assert costs[k] <= gc, "DP seam dearer than the greedy seam"
+        if check_brute:
+            bs, bc = py_brute_seam(e)
+            assert s.tolist() == bs.tolist() and costs[k] == bc
+        nxt = np.stack([np.delete(cur[i], s[i], axis=0) for i in range(H)])
+        # band property: after removing s, the energy changes only at new columns s_i-1 and s_i
+        e2 = o.energy(nxt)
+        for i in range(H):
+            for x in range(w - 1):
+                if x in (s[i] - 1, s[i]):
+                    continue
+                assert e2[i, x] == e[i, x + (1 if x >= s[i] else 0)], ("band", k, i, x)
+        cur = nxt
+    assert np.array_equal(out, cur), "carved image != input with the seams deleted"
+    return seams, costs
+
+
+def pin_carve_invariants(o):
+    rng = np.random.default_rng(8)
+    for (H, W, C, tw) in [(9, 13, 3, 6), (1, 7, 3, 2), (8, 1, 3, 1), (6, 6, 1, 1), (5, 10, 4, 3)]:
+        for alpha in (2, 256):
+            img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+            carve_invariants(o, img, tw)
+
+
+def pin_carve_hv(o):
+    rng = np.random.default_rng(9)
+    img = rng.integers(0, 5, size=(9, 11, 3), dtype=np.uint8)
+    out, vs, vc, hs, hc = o.carve_hv(img, 7, 5)
+    a, s1, c1 = o.carve(img, 7)
+    t, s2, c2 = o.carve(np.transpose(a, (1, 0, 2)).copy(), 5)
+    assert np.array_equal(out, np.transpose(t, (1, 0, 2)))
+    assert np.array_equal(vs, s1) and np.array_equal(vc, c1) and np.array_equal(hs, s2) and np.array_equal(hc, c2)
+    out, vs, vc, hs, hc = o.carve_hv(img, 8, 9)
+    assert np.array_equal(out, o.carve(img, 8)[0]) and hs.shape == (0, 8)
+
+
+ALL_PINS = [pin_hand_grids, pin_pixel_grid, pin_bruteforce, pin_energy_closed_forms, pin_energy_symmetry,
+            pin_carve_closed_forms, pin_carve_invariants, pin_carve_hv]
