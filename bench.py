@@ -1,0 +1,259 @@
+"""Benchmark of the seam-carving hot path on one MI355X.
+
+Workload (one "step"): the batched configuration -- 256 RGB uint8 blob+noise images with
+H and W each uniform in [240, 2160] (seed 3), each removing a uniform 10-40 % of its width --
+carved in one launch: the energy pass (src -> img copy + e1 energy of every image) and the
+persistent carve kernel running every image's seam loop (DP sweep, argmin, backtrack, removal,
+band energy).  Inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line: throughput in pixel-seams/s (one pixel-seam = one pixel of the current
+image swept by one seam iteration), the HBM roofline of the carve kernel (algorithmic bytes of
+the byte model / measured kernel time, against 8 TB/s), per-image completion latency p50/p99
+inside the batch, the plain per-image path (sequential sc_carve calls) on a sample, and the CPU
+oracle timed on the host cores on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-plain] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "pixel-seams removed/sec + HBM GB/s %peak; p50/p99 carve latency, batched vs plain"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "carve_batch_c4_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_21207_amd", "csrc", f)
+                  for f in ("sc_kernels.hip", "sc_internal.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def byte_model(H: int, W: int, seams: np.ndarray) -> int:
+    """Algorithmic HBM bytes of the carve loop of one image (C = 3), from its recorded seams.
+
+    Per seam on an image of current width w: the DP reads the uint16 energy plane and writes a
+    2-bit direction per cell (2.25 B per pixel); removal reads and writes, right of the seam,
+    3 RGB bytes and 2 energy bytes per pixel (10 B per shifted pixel).
+    """
+    k = seams.shape[0]
+    total = 0
+    for j in range(k):
+        w = W - j
+        total += int(2.25 * H * w) + 10 * int((w - 1 - seams[j].astype(np.int64)).sum())
+    return total
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--team", type=int, default=None)
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--n", type=int, default=256, help="images in the batch (256 = the configuration)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=24)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(images are independent: a multi-GPU run would shard the job list by work)", flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    dev = torch.device("cuda:0")
+    jobs = synth.batch_jobs(n=args.n)
+    t0 = time.time()
+    imgs_np = [j.image() for j in jobs]
+    log(f"generated {len(jobs)} images in {time.time() - t0:.1f}s")
+    srcs = [torch.from_numpy(a).to(dev) for a in imgs_np]
+    dsts = [torch.empty_like(s) for s in srcs]
+    targets = [j.target_w for j in jobs]
+    pixel_seams = sum(j.pixel_seams for j in jobs)
+    seams_total = sum(j.seams for j in jobs)
+    torch.cuda.synchronize()
+
+    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant)
+    stream = torch.cuda.current_stream()
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        bc.launch_energy()
+        if evs is not None:
+            evs[1].record(stream)
+        bc.launch_carve()
+        if evs is not None:
+            evs[2].record(stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i} done")
+    status = bc.status()
+    assert all(s == 0 for s in status), f"device status {status}"
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall * 1000.0 / args.steps
+    energy_ms = [e[0].elapsed_time(e[1]) for e in events]
+    carve_ms = [e[1].elapsed_time(e[2]) for e in events]
+    log(f"steps: {ms_per_step:.1f} ms/step; energy pass {np.mean(energy_ms):.2f} ms; carve {np.mean(carve_ms):.1f} ms")
+
+    # per-image completion latency inside the batch (device clock, from the first image's start)
+    times = bc.times()
+    t_first = min(tb for tb, _ in times)
+    lat_ms = [(te - t_first) * 1000.0 for _, te in times]
+    run_ms = [(te - tb) * 1000.0 for tb, te in times]
+
+    # algorithmic bytes of one carve launch, from the recorded seams
+    res = bc.results()
+    model_bytes = 0
+    for j, (_, seams, _) in zip(jobs, res):
+        if seams is not None:
+            model_bytes += byte_model(j.h, j.w, seams.cpu().numpy())
+    carve_s = float(np.mean(carve_ms)) / 1000.0
+    achieved = model_bytes / carve_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "kernel": "carve_batch_kernel", "model_bytes_per_launch": model_bytes,
+                "kernel_ms": round(float(np.mean(carve_ms)), 3)}
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash():
+            roofline["traffic"] = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": round(pixel_seams / (ms_per_step / 1000.0), 1),
+        "unit": "pixel-seams/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batched carve: {len(jobs)} RGB uint8 blob+noise images, H,W~U[240,2160], "
+                               "10-40% of width removed (seed 3)",
+                   "images": len(jobs), "seams": seams_total, "pixel_seams": pixel_seams,
+                   "team": bc.info.team, "variant": api.variants()[bc.info.variant]},
+        "roofline": roofline,
+        "hbm_gbps_step": round(model_bytes / (ms_per_step / 1000.0) / 1e9, 1),
+        "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
+                       "max": round(max(lat_ms), 2), "per_image_run_p50": round(pct(run_ms, 50), 2)},
+        "energy_pass_ms": round(float(np.mean(energy_ms)), 3),
+    }
+
+    # graph replay of the same launch (informative)
+    try:
+        bc.capture()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        bc.replay()
+        torch.cuda.synchronize()
+        out["graph_replay_ms"] = round((time.perf_counter() - tg) * 1000.0, 3)
+    except Exception as ex:  # pragma: no cover - informative only
+        out["graph_replay_ms"] = f"unavailable: {ex}"
+
+    if not args.no_plain:
+        # plain path: sequential sc_carve calls on one stream over a seeded sample of the images
+        rng = np.random.default_rng(0)
+        idx = sorted(rng.choice(len(jobs), size=min(args.plain_sample, len(jobs)), replace=False).tolist())
+        ws = api.workspace(max(api._lib.load().sc_workspace_bytes(jobs[i].h, jobs[i].w, 3) for i in idx), dev)
+        plat = []
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i in idx:
+            ti = time.perf_counter()
+            api.carve(dsts[i], targets[i], src=srcs[i], record=False, team=args.team, variant=args.variant, ws=ws)
+            torch.cuda.synchronize()
+            plat.append((time.perf_counter() - ti) * 1000.0)
+        tp = time.perf_counter() - tp
+        ps = sum(jobs[i].pixel_seams for i in idx)
+        out["plain"] = {"value": round(ps / tp, 1), "unit": "pixel-seams/s", "sample_images": len(idx),
+                        "per_image_ms_p50": round(pct(plat, 50), 2), "per_image_ms_p99": round(pct(plat, 99), 2),
+                        "batched_speedup": round((pixel_seams / (ms_per_step / 1000.0)) / (ps / tp), 2)}
+        log(f"plain: {out['plain']}")
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, res, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(jobs, imgs_np, gpu_results, seconds):
+    """The oracle, as it stands, on a bounded sample of the same workload on the host cores."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    # sample: the images in job order, up to ~seconds of work per core at ~1e8 pixel-seams/s per core
+    budget = seconds * 1e8 * cores
+    idx, acc = [], 0
+    for i, j in enumerate(jobs):
+        if acc + j.pixel_seams > budget and idx:
+            continue
+        idx.append(i)
+        acc += j.pixel_seams
+        if acc >= budget * 0.9:
+            break
+    oracle.default()
+
+    def run(i):
+        return oracle.carve(imgs_np[i], jobs[i].target_w)
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        outs = list(ex.map(run, idx))
+    dt = time.perf_counter() - t
+    agree = all(np.array_equal(o[1], gpu_results[i][1].cpu().numpy()) for o, i in zip(outs, idx))
+    return {"value": round(acc / dt, 1), "unit": "pixel-seams/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(idx)} of the {len(jobs)} batch images (job order, ~{seconds:.0f}s per core), "
+                      f"full carves, one image per thread, {dt:.1f}s wall",
+            "seams_match_gpu": bool(agree)}
+
+
+if __name__ == "__main__":
+    main()

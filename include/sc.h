@@ -1,0 +1,201 @@
+/*
+ * sc.h -- C ABI of the MI355X seam-carving library (libseamcarve.so).
+ *
+ * Method: arXiv 2410.21207, "Analysis of Different Algorithmic Design
+ * Techniques for Seam Carving".  The library runs the per-seam loop of that
+ * paper on one gfx950 GPU: e1 gradient energy, the dynamic-programming
+ * cumulative minimum-energy map M(i,j) = e(i,j) + min(M(i-1,j-1..j+1)), the
+ * argmin of its last row, the backtrack, and the removal of the seam.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers owned by the caller unless a comment says
+ *     "host".  The library never allocates or frees caller memory; every
+ *     scratch buffer comes from the caller's workspace `ws` (size from the
+ *     matching *_workspace_bytes function, 256-byte aligned).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls validate
+ *     their arguments synchronously, enqueue their kernels on `stream` and
+ *     return; results are ready once the stream has been synchronised.
+ *   - Images are uint8, H rows of `pitch` bytes, pixel (y,x) channel c at
+ *     img[y*pitch + x*C + c]; C in {1,2,3,4}; pitch >= W*C.
+ *   - Energies are the e1 energy of the paper: sum over channels of
+ *     |I(y,x+1)-I(y,x-1)| + |I(y+1,x)-I(y-1,x)| with indices clamped to the
+ *     image (a border pixel takes a one-sided difference).
+ *   - Seams are int32 column indices, one per row, top to bottom, in the
+ *     coordinates of the image the seam was removed from.  Ties: the leftmost
+ *     upper neighbour in the DP and the leftmost column of the last row, so the
+ *     seam is unique (the minimum of the key (cost, s[H-1], ..., s[0])).
+ *   - Limits: 1 <= H, W; H*510*C <= 8388000 (the cumulative cost of a column
+ *     must fit 23 bits); W <= 65535.  Violations return SC_EUNSUPPORTED.
+ *   - Errors are negative return codes; sc_last_error() gives the text.  No
+ *     C++ exception crosses the ABI.  Device-side failures (a team barrier
+ *     that timed out) are reported through sc_read_status().
+ *   - Thread safety: calls are reentrant; calls that share a workspace must be
+ *     ordered on one stream.
+ */
+#ifndef SEAMCARVE_SC_H
+#define SEAMCARVE_SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sc_status;
+enum {
+    SC_OK = 0,
+    SC_EINVAL = -1,      /* bad argument or shape */
+    SC_ENOMEM = -2,      /* workspace too small */
+    SC_EHIP = -3,        /* a HIP runtime call failed */
+    SC_EBUSY = -4,       /* reserved for admission control */
+    SC_EUNSUPPORTED = -5 /* outside the limits above */
+};
+
+/* Text of the last error on this thread (host memory, valid until the next sc_* call). */
+const char* sc_last_error(void);
+
+/* Library version string (host memory, static). */
+const char* sc_version(void);
+
+/*
+ * Workspace bytes for sc_carve / sc_dp_seam on an image of H x W with C
+ * channels (pure host function, no device access).  Returns 0 on bad args.
+ */
+size_t sc_workspace_bytes(int H, int W, int C);
+
+/*
+ * e1 energy map (sec. "Energy Mapping", first bullet of the paper).
+ *   img    : H x W x C image, row pitch `pitch` bytes (read only).
+ *   energy : H*W int32, dense row-major, written.
+ */
+sc_status sc_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t* energy, void* stream);
+
+/*
+ * Minimum vertical seam of a given energy map: the DP recurrence of the DP
+ * section, the bottom-row argmin and the backtrack of Alg. 3.
+ *   energy   : H*W int32, dense (read only).  Precondition: 0 <= e <= 65535
+ *              and H*max(e) <= 8388000; otherwise the seam is unspecified
+ *              (no fault).
+ *   seam     : H int32, written.
+ *   cost     : 1 int64, written (sum of e along the seam).
+ *   dirs_out : nullable; H*W uint8 receives the parent direction of every
+ *              cell (0 = upper-left, 1 = up, 2 = upper-right; row 0 is 1).
+ *   ws       : workspace of at least sc_workspace_bytes(H, W, 1) bytes.
+ */
+sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, uint8_t* dirs_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Remove one vertical seam (sec. "Removal of Seams"): in row i the pixels
+ * right of column seam[i] move one column left; the width becomes W-1.  In
+ * place at unchanged pitch; the bytes of the old last column stay as they were.
+ *   seam : H int32, 0 <= seam[i] < W (device; out-of-range rows are skipped).
+ */
+sc_status sc_remove_seam(uint8_t* img, int H, int W, int C, int pitch, const int32_t* seam, void* stream);
+
+/*
+ * Transpose J(x,y,c) = I(y,x,c) (reduction of horizontal to vertical seams,
+ * sec. "Design Techniques").  dst has W rows of dst_pitch >= H*C bytes.
+ * src and dst must not overlap.
+ */
+sc_status sc_transpose_u8(const uint8_t* src, int H, int W, int C, int src_pitch, uint8_t* dst, int dst_pitch,
+                          void* stream);
+
+/* Launch shape of the persistent carve kernel; NULL selects the built-in choice. */
+typedef struct {
+    int team;    /* workgroups working together on one image (>= 1) */
+    int variant; /* kernel variant id (see sc_variant_count); -1 = default */
+} sc_tune;
+
+/* Number of compiled kernel variants and a description of variant v (host memory, static). */
+int sc_variant_count(void);
+const char* sc_variant_name(int v);
+
+/*
+ * Carve one image to target_w columns by removing W-target_w vertical seams
+ * one at a time (the flowchart loop of the paper; each seam is the minimum
+ * seam of the current image).  One persistent kernel runs the whole loop on
+ * the device.
+ *   src       : nullable.  When given, the H x W x C image is read from src
+ *               (pitch `pitch`) and written to img before carving; else img is
+ *               carved in place.
+ *   img       : the image; on return the first target_w*C bytes of each row
+ *               hold the result (pitch unchanged).
+ *   seams_out : nullable, (W-target_w)*H int32; seam k at seams_out[k*H + i].
+ *   costs_out : nullable, (W-target_w) int64.
+ *   tune      : host pointer, nullable.
+ *   ws        : workspace of at least sc_workspace_bytes(H, W, C) bytes.
+ */
+sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
+                   int32_t* seams_out, int64_t* costs_out, const sc_tune* tune, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* One image of a batch (host struct; its pointers are device pointers). */
+typedef struct {
+    const uint8_t* src; /* nullable, as in sc_carve */
+    uint8_t* img;
+    int H, W, C, pitch, target_w;
+    int32_t* seams_out; /* nullable */
+    int64_t* costs_out; /* nullable */
+} sc_job;
+
+/* Workspace bytes for a batch of n jobs (host array). 0 on bad args. */
+size_t sc_batch_workspace_bytes(const sc_job* jobs, int n);
+
+/* Summary of a prepared batch (host struct, filled by sc_batch_prepare). */
+typedef struct {
+    int n;        /* images */
+    int nblocks;  /* workgroups of the carve launch */
+    int variant;  /* kernel variant */
+    int max_rows; /* tallest image */
+    int team;     /* workgroups per image */
+    int pad0;
+    size_t off_imgs, off_blk, off_teams, off_team_imgs; /* plan arrays inside ws */
+} sc_batch_info;
+
+/*
+ * Batched carve, split in two so that the launch can be captured in a HIP
+ * graph and replayed:
+ *   sc_batch_prepare validates the jobs, plans which workgroups carve which
+ *   image (images ordered by work, longest first; the workgroups of one team
+ *   placed on one XCD) and writes the plan into ws with a synchronous copy;
+ *   `info` (host) receives the summary that sc_batch_launch needs.
+ *   sc_batch_launch enqueues the energy and carve kernels for that plan; it
+ *   makes no host-to-device copy and allocates nothing.  Replaying it carves
+ *   the jobs again from their src (jobs without src would be carved twice).
+ *   tune: host pointer, nullable.
+ */
+sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void* ws, size_t ws_bytes,
+                           sc_batch_info* info);
+sc_status sc_batch_launch(const sc_batch_info* info, void* ws, void* stream);
+
+/* The two passes of sc_batch_launch, for callers that time them apart:
+ * the energy pass (zero control words, copy src -> img, e1 energy of every image) and the
+ * carve pass (the persistent kernel running the seam loop of every image). */
+sc_status sc_batch_launch_energy(const sc_batch_info* info, void* ws, void* stream);
+sc_status sc_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream);
+
+/* prepare + launch. */
+sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/*
+ * Device-side status of the images of a workspace (synchronous: waits for the
+ * device).  flags[i] for image i (n = 1 for sc_carve/sc_dp_seam workspaces):
+ * 0 = fine, bit 0 = a team barrier timed out (the results of that image are
+ * invalid).  Returns the number of images written.
+ */
+int sc_read_status(const void* ws, uint32_t* flags, int max_n);
+
+/*
+ * Device clock stamps of the images of a workspace (synchronous): t_begin[i] / t_end[i] are
+ * the constant-rate device clock (s_memrealtime) when the carve of image i started and ended;
+ * *hz receives that clock's rate.  Returns the number of images written, -1 on error.
+ */
+int sc_read_times(const void* ws, uint64_t* t_begin, uint64_t* t_end, int max_n, double* hz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEAMCARVE_SC_H */

@@ -1,0 +1,243 @@
+"""Torch-facing helpers over the C ABI (PyTorch is used only for device memory and streams).
+
+Images are CUDA/HIP uint8 tensors [H, W, C] whose rows may be padded (stride(0) = pitch
+bytes, stride(1) = C, stride(2) = 1).  Every function here only marshals arguments into the
+C entry points of libseamcarve.so; all computation happens in its HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+__all__ = ["energy", "dp_seam", "remove_seam", "transpose", "carve", "carve_hv", "workspace",
+           "BatchCarver", "variants", "read_status"]
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _image(t: torch.Tensor, name="img"):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or t.dim() != 3 or not t.is_cuda:
+        raise ValueError(f"{name} must be a uint8 [H, W, C] tensor on the GPU")
+    H, W, C = t.shape
+    if t.stride(2) != 1 or t.stride(1) != C:
+        raise ValueError(f"{name} pixels must be packed (stride(1) == C, stride(2) == 1)")
+    return H, W, C, t.stride(0)
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A fresh byte buffer for a workspace (the caching allocator aligns blocks to >= 512 B)."""
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def variants():
+    lib = _lib.load()
+    return [lib.sc_variant_name(v).decode() for v in range(lib.sc_variant_count())]
+
+
+def energy(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """e1 energy map, int32 [H, W]."""
+    H, W, C, pitch = _image(img)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int32, device=img.device)
+    _lib.call("sc_energy", _ptr(img), H, W, C, pitch, _ptr(out), _stream(stream))
+    return out
+
+
+def dp_seam(e: torch.Tensor, dirs: bool = False, ws: torch.Tensor | None = None, stream=None):
+    """Minimum vertical seam of an int32 [H, W] energy map -> (seam int32 [H], cost int64 [1][, dirs uint8 [H, W]])."""
+    if e.dtype != torch.int32 or e.dim() != 2 or not e.is_cuda:
+        raise ValueError("energy must be an int32 [H, W] GPU tensor")
+    e = e.contiguous()
+    H, W = e.shape
+    lib = _lib.load()
+    need = lib.sc_workspace_bytes(H, W, 1)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, e.device)
+    seam = torch.empty(H, dtype=torch.int32, device=e.device)
+    cost = torch.empty(1, dtype=torch.int64, device=e.device)
+    d = torch.empty((H, W), dtype=torch.uint8, device=e.device) if dirs else None
+    _lib.call("sc_dp_seam", _ptr(e), H, W, _ptr(seam), _ptr(cost), _ptr(d), _ptr(ws), ws.numel(), _stream(stream))
+    return (seam, cost, d) if dirs else (seam, cost)
+
+
+def remove_seam(img: torch.Tensor, seam: torch.Tensor, stream=None) -> torch.Tensor:
+    """Remove one vertical seam in place; returns the view img[:, :W-1]."""
+    H, W, C, pitch = _image(img)
+    if seam.dtype != torch.int32 or seam.numel() != H or not seam.is_cuda:
+        raise ValueError("seam must be an int32 [H] GPU tensor")
+    _lib.call("sc_remove_seam", _ptr(img), H, W, C, pitch, _ptr(seam.contiguous()), _stream(stream))
+    return img[:, : W - 1]
+
+
+def transpose(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """J(x, y, c) = I(y, x, c) -> uint8 [W, H, C]."""
+    H, W, C, pitch = _image(img)
+    if out is None:
+        out = torch.empty((W, H, C), dtype=torch.uint8, device=img.device)
+    _, _, _, opitch = _image(out, "out")
+    _lib.call("sc_transpose_u8", _ptr(img), H, W, C, pitch, _ptr(out), opitch, _stream(stream))
+    return out
+
+
+def _tune(team=None, variant=None):
+    if team is None and variant is None:
+        return None
+    return ctypes.byref(_lib.sc_tune(team or 1, -1 if variant is None else variant))
+
+
+def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,
+          team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None):
+    """Carve `img` to target_w columns (in place; from `src` when given).
+
+    Returns (img[:, :target_w], seams int32 [k, H] or None, costs int64 [k] or None).
+    """
+    H, W, C, pitch = _image(img)
+    if src is not None:
+        sH, sW, sC, spitch = _image(src, "src")
+        if (sH, sW, sC, spitch) != (H, W, C, pitch):
+            raise ValueError("src must have the shape and pitch of img")
+    k = W - int(target_w)
+    lib = _lib.load()
+    need = lib.sc_workspace_bytes(H, W, C)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, img.device)
+    seams = costs = None
+    if record and k > 0:
+        seams = torch.empty((k, H), dtype=torch.int32, device=img.device)
+        costs = torch.empty(k, dtype=torch.int64, device=img.device)
+    _lib.call("sc_carve", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
+              _tune(team, variant), _ptr(ws), ws.numel(), _stream(stream))
+    return img[:, : int(target_w)], seams, costs
+
+
+def carve_hv(img: torch.Tensor, target_w: int, target_h: int, record: bool = True, team=None, variant=None,
+             stream=None):
+    """Vertical seams to target_w (in place), then horizontal seams via a transpose to target_h.
+
+    Returns (out [target_h, target_w, C] new tensor, vseams, vcosts, hseams, hcosts).
+    """
+    H, W, C, _ = _image(img)
+    a, vs, vc = carve(img, target_w, record=record, team=team, variant=variant, stream=stream)
+    t = transpose(a, stream=stream)                       # [target_w, H, C]
+    b, hs, hc = carve(t, target_h, record=record, team=team, variant=variant, stream=stream)
+    out = transpose(b, stream=stream)                     # [target_h, target_w, C]
+    return out, vs, vc, hs, hc
+
+
+def read_status(ws: torch.Tensor, n: int = 1):
+    """Device status flags of the images of a workspace (synchronises the device)."""
+    flags = (ctypes.c_uint32 * n)()
+    got = _lib.load().sc_read_status(_ptr(ws), flags, n)
+    if got < 0:
+        raise _lib.ScError(got, "sc_read_status", _lib.load().sc_last_error().decode())
+    return list(flags)[:got]
+
+
+def read_times(ws: torch.Tensor, n: int = 1):
+    """[(t_begin_s, t_end_s)] per image of the last carve in this workspace (synchronises)."""
+    tb = (ctypes.c_uint64 * n)()
+    te = (ctypes.c_uint64 * n)()
+    hz = ctypes.c_double(0)
+    got = _lib.load().sc_read_times(_ptr(ws), tb, te, n, ctypes.byref(hz))
+    if got < 0:
+        raise _lib.ScError(got, "sc_read_times", _lib.load().sc_last_error().decode())
+    return [(tb[i] / hz.value, te[i] / hz.value) for i in range(got)]
+
+
+@dataclass
+class _Job:
+    src: torch.Tensor | None
+    img: torch.Tensor
+    target_w: int
+    seams: torch.Tensor | None
+    costs: torch.Tensor | None
+
+
+class BatchCarver:
+    """Carve many images of uneven sizes in one persistent launch.
+
+    ``prepare()`` plans the launch (synchronous upload of the plan into the workspace);
+    ``launch()`` enqueues it (no host-to-device copy, no allocation), so it can be captured
+    in a HIP graph with ``capture()`` and replayed with ``replay()``.
+    """
+
+    def __init__(self, imgs, targets, srcs=None, record: bool = True, team: int | None = None,
+                 variant: int | None = None):
+        self.jobs = []
+        for i, (img, tw) in enumerate(zip(imgs, targets)):
+            H, W, C, pitch = _image(img)
+            src = None if srcs is None else srcs[i]
+            if src is not None and _image(src, "src") != (H, W, C, pitch):
+                raise ValueError("src must have the shape and pitch of img")
+            k = W - int(tw)
+            seams = torch.empty((k, H), dtype=torch.int32, device=img.device) if record and k > 0 else None
+            costs = torch.empty(k, dtype=torch.int64, device=img.device) if record and k > 0 else None
+            self.jobs.append(_Job(src, img, int(tw), seams, costs))
+        n = len(self.jobs)
+        self._cjobs = (_lib.sc_job * n)()
+        for i, j in enumerate(self.jobs):
+            H, W, C, pitch = _image(j.img)
+            self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
+                                         pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
+                                         None if j.costs is None else j.costs.data_ptr())
+        self._tune = _lib.sc_tune(team or 1, -1 if variant is None else variant)
+        need = _lib.load().sc_batch_workspace_bytes(self._cjobs, n)
+        if need == 0:
+            raise ValueError("bad batch")
+        self.ws = workspace(need, self.jobs[0].img.device)
+        self.info = _lib.sc_batch_info()
+        self.graph = None
+        self.prepare()
+
+    def prepare(self):
+        _lib.call("sc_batch_prepare", self._cjobs, len(self.jobs), ctypes.byref(self._tune), _ptr(self.ws),
+                  self.ws.numel(), ctypes.byref(self.info))
+
+    def launch(self, stream=None):
+        _lib.call("sc_batch_launch", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def launch_energy(self, stream=None):
+        _lib.call("sc_batch_launch_energy", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def launch_carve(self, stream=None):
+        _lib.call("sc_batch_launch_carve", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def times(self):
+        """Per-image (begin, end) of the last carve in seconds of the device clock."""
+        return read_times(self.ws, len(self.jobs))
+
+    def capture(self):
+        """Capture launch() in a CUDA/HIP graph (requires every job to have a src)."""
+        if any(j.src is None for j in self.jobs):
+            raise ValueError("graph replay needs src images (in-place jobs would be carved twice)")
+        self.graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.graph.capture_begin()
+            self.launch(stream=s)
+            self.graph.capture_end()
+        torch.cuda.current_stream().wait_stream(s)
+        return self.graph
+
+    def replay(self):
+        self.graph.replay()
+
+    def results(self):
+        return [(j.img[:, : j.target_w], j.seams, j.costs) for j in self.jobs]
+
+    def status(self):
+        return read_status(self.ws, len(self.jobs))

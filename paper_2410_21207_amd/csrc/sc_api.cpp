@@ -1,0 +1,459 @@
+// C ABI of libseamcarve: argument validation, workspace layout, batch planning, launches.
+// Declarations and the meaning of every argument: include/sc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+#include "../../include/sc.h"
+#include "sc_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sc_status fail(sc_status code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+sc_status ok() {
+    g_err[0] = 0;
+    return SC_OK;
+}
+
+sc_status hip_fail(hipError_t e, const char* what) {
+    return fail(SC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Workspace header: the first 256 bytes of every workspace, then one Ctl per image.
+struct WsHead {
+    uint32_t magic;
+    int32_t n;
+    uint32_t pad[62];
+};
+constexpr uint32_t kMagic = sc::kWsMagic;
+static_assert(sizeof(WsHead) == sc::kWsHeadBytes, "header size");
+static_assert(sizeof(sc::Ctl) == 64, "ctl size");
+
+constexpr int kMaxCostBound = 8388000;  // H*510*C: the column cost must fit 23 bits
+
+sc_status check_image(int H, int W, int C, int pitch) {
+    if (H < 1 || W < 1) return fail(SC_EINVAL, "H=%d W=%d must be >= 1", H, W);
+    if (C < 1 || C > 4) return fail(SC_EINVAL, "C=%d must be in 1..4", C);
+    if ((long long)pitch < (long long)W * C) return fail(SC_EINVAL, "pitch=%d < W*C=%lld", pitch, (long long)W * C);
+    if (W > 65535) return fail(SC_EUNSUPPORTED, "W=%d > 65535", W);
+    if ((long long)H * 510 * C > kMaxCostBound)
+        return fail(SC_EUNSUPPORTED, "H*510*C=%lld exceeds %d (23-bit cumulative cost)", (long long)H * 510 * C,
+                    kMaxCostBound);
+    return SC_OK;
+}
+
+size_t ctl_region(int n) { return sc::align_up(sizeof(WsHead) + (size_t)n * sizeof(sc::Ctl), sc::kAlign); }
+
+// Fill the device descriptor of one image whose scratch starts at `base` and whose Ctl is `ctl`.
+sc::Img make_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
+                 int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl, int kr, int G, int mode) {
+    const sc::Layout L = sc::layout_for(H, W, 32);
+    sc::Img d;
+    memset(&d, 0, sizeof(d));
+    d.src = src;
+    d.img = img;
+    d.pitch = pitch;
+    d.H = H;
+    d.W = W;
+    d.C = C;
+    d.target_w = target_w;
+    d.seams_out = seams_out;
+    d.costs_out = reinterpret_cast<long long*>(costs_out);
+    d.e = reinterpret_cast<uint16_t*>(base + L.e);
+    d.dirs = reinterpret_cast<uint8_t*>(base + L.dirs);
+    d.anc = reinterpret_cast<int8_t*>(base + L.anc);
+    d.xq = reinterpret_cast<uint32_t*>(base + L.xq);
+    d.seam = reinterpret_cast<int32_t*>(base + L.seam);
+    d.amin = &ctl->amin;
+    d.bar = &ctl->bar;
+    d.status = &ctl->status;
+    d.ep = L.ep;
+    d.db = L.db;
+    d.xw = L.xw;
+    d.P = (H + kr - 1) / kr;
+    d.G = G;
+    d.mode = mode;
+    return d;
+}
+
+int resolve_variant(const sc_tune* t) {
+    if (t && t->variant >= 0) return t->variant < sc::variant_count() ? t->variant : -1;
+    return sc::default_variant();
+}
+
+}  // namespace
+
+namespace sc {
+
+Layout layout_for(int H, int W, int kr_min) {
+    Layout L;
+    const int P = (H + kr_min - 1) / kr_min;
+    L.P = P;
+    L.ep = (int)align_up((size_t)W + 8, 64);
+    L.db = (int)align_up((size_t)(W + 3) / 4 + 4, 16);
+    L.xw = (int)align_up((size_t)W + 16, 64);
+    size_t off = 0;
+    L.ctl = 0;
+    L.e = off;
+    off = align_up(off + (size_t)H * L.ep * 2, kAlign);
+    L.dirs = off;
+    off = align_up(off + (size_t)H * L.db, kAlign);
+    L.anc = off;
+    off = align_up(off + (size_t)P * W, kAlign);
+    L.xq = off;
+    off = align_up(off + (size_t)2 * L.xw * 4, kAlign);
+    L.seam = off;
+    off = align_up(off + (size_t)H * 4, kAlign);
+    L.total = off;
+    return L;
+}
+
+}  // namespace sc
+
+extern "C" {
+
+const char* sc_last_error(void) { return g_err; }
+
+const char* sc_version(void) { return "seamcarve-mi355x 0.1 (gfx950)"; }
+
+int sc_variant_count(void) { return sc::variant_count(); }
+
+const char* sc_variant_name(int v) {
+    if (v < 0 || v >= sc::variant_count()) return "";
+    return sc::variant(v).name;
+}
+
+size_t sc_workspace_bytes(int H, int W, int C) {
+    if (H < 1 || W < 1 || C < 1 || C > 4) return 0;
+    return ctl_region(1) + sc::layout_for(H, W, 32).total;
+}
+
+sc_status sc_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t* energy, void* stream) {
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (!img || !energy) return fail(SC_EINVAL, "null pointer");
+    hipError_t e = sc::launch_energy_i32(img, H, W, C, pitch, energy, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    return ok();
+}
+
+sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, uint8_t* dirs_out, void* ws,
+                     size_t ws_bytes, void* stream) {
+    sc_status s = check_image(H, W, 1, W);
+    if (s != SC_OK) return s;
+    if (!energy || !seam || !cost || !ws) return fail(SC_EINVAL, "null pointer");
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const size_t need = sc_workspace_bytes(H, W, 1);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    const int v = sc::default_variant();
+    char* base = static_cast<char*>(ws);
+    sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
+    sc::Img d = make_img(nullptr, nullptr, H, W, 1, W, W > 1 ? W - 1 : 1, seam, cost, base + ctl_region(1), ctl,
+                         sc::variant(v).kr, 1, 1);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sc::launch_prepare_from_i32(d, energy, st);
+    if (e == hipSuccess) e = sc::launch_carve_single(d, v, 1, st);
+    if (e == hipSuccess && dirs_out) e = sc::launch_unpack_dirs(d, dirs_out, st);
+    if (e != hipSuccess) return hip_fail(e, "dp launch");
+    return ok();
+}
+
+sc_status sc_remove_seam(uint8_t* img, int H, int W, int C, int pitch, const int32_t* seam, void* stream) {
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (!img || !seam) return fail(SC_EINVAL, "null pointer");
+    hipError_t e = sc::launch_remove_seam(img, H, W, C, pitch, seam, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "remove launch");
+    return ok();
+}
+
+sc_status sc_transpose_u8(const uint8_t* src, int H, int W, int C, int src_pitch, uint8_t* dst, int dst_pitch,
+                          void* stream) {
+    if (H < 1 || W < 1 || C < 1 || C > 4) return fail(SC_EINVAL, "bad shape H=%d W=%d C=%d", H, W, C);
+    if ((long long)src_pitch < (long long)W * C || (long long)dst_pitch < (long long)H * C)
+        return fail(SC_EINVAL, "pitch too small");
+    if (!src || !dst) return fail(SC_EINVAL, "null pointer");
+    const uintptr_t s0 = (uintptr_t)src, s1 = s0 + (size_t)(H - 1) * src_pitch + (size_t)W * C;
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (size_t)(W - 1) * dst_pitch + (size_t)H * C;
+    if (s0 < d1 && d0 < s1) return fail(SC_EINVAL, "src and dst overlap");
+    hipError_t e = sc::launch_transpose(src, H, W, C, src_pitch, dst, dst_pitch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "transpose launch");
+    return ok();
+}
+
+sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
+                   int32_t* seams_out, int64_t* costs_out, const sc_tune* tune, void* ws, size_t ws_bytes,
+                   void* stream) {
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (!img || !ws) return fail(SC_EINVAL, "null pointer");
+    if (target_w < 1 || target_w > W) return fail(SC_EINVAL, "target_w=%d not in [1, W=%d]", target_w, W);
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const size_t need = sc_workspace_bytes(H, W, C);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    const int v = resolve_variant(tune);
+    if (v < 0) return fail(SC_EINVAL, "unknown kernel variant %d", tune->variant);
+    const int G = tune && tune->team > 0 ? tune->team : 1;
+    if (G > 32) return fail(SC_EUNSUPPORTED, "team of %d workgroups > 32", G);
+    char* base = static_cast<char*>(ws);
+    sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
+    sc::Img d = make_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out, base + ctl_region(1), ctl,
+                         sc::variant(v).kr, G, 0);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sc::launch_prepare_single(d, st);
+    if (e == hipSuccess && target_w < W) e = sc::launch_carve_single(d, v, G, st);
+    if (e != hipSuccess) return hip_fail(e, "carve launch");
+    return ok();
+}
+
+size_t sc_batch_workspace_bytes(const sc_job* jobs, int n) {
+    if (!jobs || n < 1) return 0;
+    size_t total = ctl_region(n);
+    total += sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
+    // plan arrays: blocks (<= 8 * n * 32 int2), teams (n int2), team images (n int)
+    total += sc::align_up((size_t)8 * 32 * n * sizeof(int2), sc::kAlign);
+    total += sc::align_up((size_t)n * sizeof(int2), sc::kAlign);
+    total += sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].H < 1 || jobs[i].W < 1) return 0;
+        total += sc::layout_for(jobs[i].H, jobs[i].W, 32).total;
+    }
+    return total;
+}
+
+sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void* ws, size_t ws_bytes,
+                           sc_batch_info* info) {
+    if (!jobs || n < 1 || !ws || !info) return fail(SC_EINVAL, "null pointer or n < 1");
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    for (int i = 0; i < n; ++i) {
+        const sc_job& j = jobs[i];
+        sc_status s = check_image(j.H, j.W, j.C, j.pitch);
+        if (s != SC_OK) return fail(s, "job %d: %s", i, g_err);
+        if (!j.img) return fail(SC_EINVAL, "job %d: null image", i);
+        if (j.target_w < 1 || j.target_w > j.W) return fail(SC_EINVAL, "job %d: target_w=%d not in [1, %d]", i,
+                                                            j.target_w, j.W);
+    }
+    const size_t need = sc_batch_workspace_bytes(jobs, n);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    const int v = resolve_variant(tune);
+    if (v < 0) return fail(SC_EINVAL, "unknown kernel variant %d", tune->variant);
+    int G = tune && tune->team > 0 ? tune->team : 1;
+    if (G > 32) return fail(SC_EUNSUPPORTED, "team of %d workgroups > 32", G);
+
+    // work of every image: pixel-seams = sum over seams of the current image's pixels
+    std::vector<double> work(n);
+    for (int i = 0; i < n; ++i) {
+        const double k = jobs[i].W - jobs[i].target_w;
+        work[i] = (double)jobs[i].H * (k * jobs[i].W - k * (k - 1) / 2) + 1.0;
+    }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+
+    std::vector<int2> blk, teams;
+    std::vector<int> team_imgs;
+    if (G == 1) {
+        // one workgroup per image, launched longest first: the dispatcher hands out the next
+        // image whenever a workgroup slot frees up (longest-processing-time-first order).
+        for (int t = 0; t < n; ++t) {
+            blk.push_back(make_int2(t, 0));
+            teams.push_back(make_int2(t, 1));
+            team_imgs.push_back(order[t]);
+        }
+    } else {
+        // Teams of G workgroups must be resident together: size the grid to the occupancy.
+        int dev = 0, ncu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "device query");
+        const int per_cu = sc::carve_blocks_per_cu(v);
+        const int capacity = per_cu * ncu;
+        int nteams = std::min(n, capacity / G);
+        if (nteams < 1) return fail(SC_EUNSUPPORTED, "team of %d exceeds %d resident workgroups", G, capacity);
+        // longest-processing-time-first assignment of images to teams
+        std::vector<std::vector<int>> lists(nteams);
+        std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>, std::greater<>> pq;
+        for (int t = 0; t < nteams; ++t) pq.push({0.0, t});
+        for (int i : order) {
+            auto top = pq.top();
+            pq.pop();
+            lists[top.second].push_back(i);
+            pq.push({top.first + work[i], top.second});
+        }
+        // place team t on XCD t % 8: its members are blocks xcd + 8 * slot, consecutive slots
+        int slots[8] = {0};
+        int nb = 0;
+        std::vector<std::pair<int, int2>> placed;
+        for (int t = 0; t < nteams; ++t) {
+            const int x = t % 8;
+            for (int r = 0; r < G; ++r) {
+                const int b = x + 8 * (slots[x] + r);
+                placed.push_back({b, make_int2(t, r)});
+                nb = std::max(nb, b + 1);
+            }
+            slots[x] += G;
+        }
+        if (nb > capacity) return fail(SC_EUNSUPPORTED, "plan needs %d resident workgroups > %d", nb, capacity);
+        blk.assign(nb, make_int2(-1, -1));
+        for (auto& pr : placed) blk[pr.first] = pr.second;
+        for (int t = 0; t < nteams; ++t) {
+            teams.push_back(make_int2((int)team_imgs.size(), (int)lists[t].size()));
+            for (int i : lists[t]) team_imgs.push_back(i);
+        }
+    }
+
+    // host image of the plan region
+    const size_t off_imgs = ctl_region(n);
+    const size_t off_blk = off_imgs + sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
+    const size_t off_teams = off_blk + sc::align_up((size_t)8 * 32 * n * sizeof(int2), sc::kAlign);
+    const size_t off_ti = off_teams + sc::align_up((size_t)n * sizeof(int2), sc::kAlign);
+    size_t off_data = off_ti + sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    if (blk.size() > (size_t)8 * 32 * n) return fail(SC_EUNSUPPORTED, "plan too large");
+    std::vector<char> host(off_data, 0);
+    WsHead* h = reinterpret_cast<WsHead*>(host.data());
+    h->magic = kMagic;
+    h->n = n;
+    char* base = static_cast<char*>(ws);
+    sc::Img* imgs = reinterpret_cast<sc::Img*>(host.data() + off_imgs);
+    int max_rows = 1;
+    for (int i = 0; i < n; ++i) {
+        const sc_job& j = jobs[i];
+        sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead)) + i;
+        imgs[i] = make_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
+                           base + off_data, ctl, sc::variant(v).kr, G, 0);
+        off_data += sc::layout_for(j.H, j.W, 32).total;
+        max_rows = std::max(max_rows, j.H);
+    }
+    memcpy(host.data() + off_blk, blk.data(), blk.size() * sizeof(int2));
+    memcpy(host.data() + off_teams, teams.data(), teams.size() * sizeof(int2));
+    memcpy(host.data() + off_ti, team_imgs.data(), team_imgs.size() * sizeof(int));
+    hipError_t e = hipMemcpy(ws, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+
+    memset(info, 0, sizeof(*info));
+    info->n = n;
+    info->nblocks = (int)blk.size();
+    info->variant = v;
+    info->max_rows = max_rows;
+    info->team = G;
+    info->off_imgs = off_imgs;
+    info->off_blk = off_blk;
+    info->off_teams = off_teams;
+    info->off_team_imgs = off_ti;
+    return ok();
+}
+
+static sc_status batch_pass(const sc_batch_info* info, void* ws, void* stream, bool energy, bool carve) {
+    if (!info || !ws || info->n < 1 || info->nblocks < 1) return fail(SC_EINVAL, "bad batch info");
+    char* base = static_cast<char*>(ws);
+    hipStream_t st = (hipStream_t)stream;
+    const sc::Img* imgs = reinterpret_cast<const sc::Img*>(base + info->off_imgs);
+    hipError_t e = hipSuccess;
+    if (energy) e = sc::launch_prepare_batch(imgs, info->n, info->max_rows, st);
+    if (e == hipSuccess && carve)
+        e = sc::launch_carve_batch(imgs, reinterpret_cast<const int2*>(base + info->off_blk),
+                                   reinterpret_cast<const int2*>(base + info->off_teams),
+                                   reinterpret_cast<const int*>(base + info->off_team_imgs), info->nblocks,
+                                   info->variant, st);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    return ok();
+}
+
+sc_status sc_batch_launch(const sc_batch_info* info, void* ws, void* stream) {
+    return batch_pass(info, ws, stream, true, true);
+}
+
+sc_status sc_batch_launch_energy(const sc_batch_info* info, void* ws, void* stream) {
+    return batch_pass(info, ws, stream, true, false);
+}
+
+sc_status sc_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream) {
+    return batch_pass(info, ws, stream, false, true);
+}
+
+sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* ws, size_t ws_bytes, void* stream) {
+    sc_batch_info info;
+    sc_status s = sc_batch_prepare(jobs, n, tune, ws, ws_bytes, &info);
+    if (s != SC_OK) return s;
+    return sc_batch_launch(&info, ws, stream);
+}
+
+int sc_read_status(const void* ws, uint32_t* flags, int max_n) {
+    if (!ws || !flags || max_n < 1) {
+        fail(SC_EINVAL, "bad arguments");
+        return -1;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        fail(SC_EHIP, "device synchronize failed");
+        return -1;
+    }
+    WsHead h;
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess || h.magic != kMagic || h.n < 1) {
+        fail(SC_EINVAL, "not a prepared workspace");
+        return -1;
+    }
+    const int n = std::min(h.n, max_n);
+    std::vector<sc::Ctl> c(n);
+    if (hipMemcpy(c.data(), static_cast<const char*>(ws) + sizeof(WsHead), n * sizeof(sc::Ctl),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+        fail(SC_EHIP, "status copy failed");
+        return -1;
+    }
+    for (int i = 0; i < n; ++i) flags[i] = c[i].status;
+    ok();
+    return n;
+}
+
+}  // extern "C"
+
+extern "C" int sc_read_times(const void* ws, uint64_t* t_begin, uint64_t* t_end, int max_n, double* hz) {
+    if (!ws || !t_begin || !t_end || max_n < 1) {
+        fail(SC_EINVAL, "bad arguments");
+        return -1;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        fail(SC_EHIP, "device synchronize failed");
+        return -1;
+    }
+    WsHead h;
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess || h.magic != kMagic || h.n < 1) {
+        fail(SC_EINVAL, "not a prepared workspace");
+        return -1;
+    }
+    const int n = std::min(h.n, max_n);
+    std::vector<sc::Ctl> c(n);
+    if (hipMemcpy(c.data(), static_cast<const char*>(ws) + sizeof(WsHead), n * sizeof(sc::Ctl),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+        fail(SC_EHIP, "times copy failed");
+        return -1;
+    }
+    for (int i = 0; i < n; ++i) {
+        t_begin[i] = c[i].t_begin;
+        t_end[i] = c[i].t_end;
+    }
+    if (hz) {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            *hz = khz * 1000.0;
+        else
+            *hz = 100e6;
+    }
+    ok();
+    return n;
+}

@@ -1,0 +1,81 @@
+// Internal structures of libseamcarve (not part of the C ABI).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace sc {
+
+// Device descriptor of one image being carved.  All pointers are device pointers.
+struct Img {
+    const uint8_t* src;  // optional source copied into img by the energy pass
+    uint8_t* img;        // H rows of `pitch` bytes, carved in place
+    long long pitch;
+    int H, W, C, target_w;
+    int32_t* seams_out;  // optional, (W-target_w)*H
+    long long* costs_out;  // optional, W-target_w
+    // workspace pieces
+    uint16_t* e;   // energy plane, H rows of `ep` uint16
+    uint8_t* dirs; // parent directions, 2 bits per cell, H rows of `db` bytes
+    int8_t* anc;   // per DP phase, the ancestor offset of every column at the phase's last row
+    uint32_t* xq;  // 2 rows of `xw` uint32: DP keys exchanged between waves at phase ends
+    int32_t* seam; // current seam, H
+    unsigned long long* amin;  // packed (cost << 32 | column) argmin of the current seam
+    unsigned* bar;             // team barrier counter
+    unsigned* status;          // error bits
+    int ep, db, xw, P;         // pitches and the number of DP phases
+    int G;                     // team size (workgroups) carving this image
+    int mode;                  // 0 = carve, 1 = one seam only, no removal (sc_dp_seam)
+    int pad0, pad1;
+};
+
+// Control words of one image (zeroed by the first pass of every launch).
+struct Ctl {
+    unsigned long long amin;
+    unsigned bar;
+    unsigned status;
+    unsigned long long t_begin, t_end;  // device clock when the carve started / ended
+    unsigned pad[8];
+};
+
+// Placement of one image's scratch inside a workspace.
+struct Layout {
+    size_t ctl, e, dirs, anc, xq, seam, total;
+    int ep, db, xw, P;
+};
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kWsMagic = 0x31574353u;  // "SCW1": first word of a prepared workspace
+constexpr size_t kWsHeadBytes = 256;        // header, then one Ctl per image
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Kernel variants: columns per lane and rows per DP phase.
+struct Variant {
+    int cpl, kr, threads;
+    const char* name;
+};
+
+Layout layout_for(int H, int W, int variant_kr_min);
+int variant_count();
+const Variant& variant(int v);
+int default_variant();
+int max_phase_rows();
+
+// Launchers (sc_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long pitch, int32_t* out,
+                             hipStream_t st);
+hipError_t launch_prepare_single(const Img& d, hipStream_t st);          // energy plane (+copy, ctl zero)
+hipError_t launch_prepare_from_i32(const Img& d, const int32_t* energy, hipStream_t st);
+hipError_t launch_carve_single(const Img& d, int variant, int G, hipStream_t st);
+hipError_t launch_unpack_dirs(const Img& d, uint8_t* out, hipStream_t st);
+hipError_t launch_remove_seam(uint8_t* img, int H, int W, int C, long long pitch, const int32_t* seam,
+                              hipStream_t st);
+hipError_t launch_transpose(const uint8_t* src, int H, int W, int C, long long sp, uint8_t* dst, long long dp,
+                            hipStream_t st);
+hipError_t launch_prepare_batch(const Img* d_imgs, int n, int max_rows, hipStream_t st);
+hipError_t launch_carve_batch(const Img* d_imgs, const int2* blk, const int2* teams, const int* team_imgs,
+                              int nblocks, int variant, hipStream_t st);
+int carve_blocks_per_cu(int variant);  // occupancy of the carve kernel
+
+}  // namespace sc

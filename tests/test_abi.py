@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol include/sc.h declares, and
+rejects bad arguments before touching a device (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_21207_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "sc.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in sc.h but not exported"
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_sizes_match_header(lib):
+    assert ctypes.sizeof(_lib.sc_job) == 8 + 8 + 5 * 4 + 4 + 8 + 8  # padding after target_w
+    assert ctypes.sizeof(_lib.sc_tune) == 8
+    assert ctypes.sizeof(_lib.sc_batch_info) == 6 * 4 + 4 * 8
+
+
+def test_workspace_sizes(lib):
+    assert lib.sc_workspace_bytes(0, 10, 3) == 0
+    assert lib.sc_workspace_bytes(10, 10, 5) == 0
+    a = lib.sc_workspace_bytes(1080, 1920, 3)
+    b = lib.sc_workspace_bytes(2160, 3840, 3)
+    assert a > 1080 * 1920 * 2 and b > 4 * a * 0.9 and a % 256 == 0
+
+
+def test_variants(lib):
+    n = lib.sc_variant_count()
+    assert n >= 1
+    assert all(lib.sc_variant_name(v) for v in range(n))
+    assert lib.sc_variant_name(n) == b""
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, 0, 5, 3, 15, FAKE, None), _lib.SC_EINVAL),          # H < 1
+    ((FAKE, 5, 5, 5, 25, FAKE, None), _lib.SC_EINVAL),          # C > 4
+    ((FAKE, 5, 5, 3, 14, FAKE, None), _lib.SC_EINVAL),          # pitch < W*C
+    ((None, 5, 5, 3, 15, FAKE, None), _lib.SC_EINVAL),          # null image
+    ((FAKE, 5483, 5, 3, 15, FAKE, None), _lib.SC_EUNSUPPORTED),  # column cost > 23 bits
+])
+def test_energy_validation(lib, args, code):
+    assert lib.sc_energy(*args) == code
+    assert lib.sc_last_error()
+
+
+def test_carve_validation(lib):
+    ws = FAKE
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 0, None, None, None, ws, 1 << 30, None) == _lib.SC_EINVAL
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 11, None, None, None, ws, 1 << 30, None) == _lib.SC_EINVAL
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 5, None, None, None, ws, 10, None) == _lib.SC_ENOMEM
+    assert b"workspace" in lib.sc_last_error()
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 5, None, None, None, ctypes.c_void_p(0x1001), 1 << 30,
+                        None) == _lib.SC_EINVAL  # misaligned workspace
+    bad = _lib.sc_tune(1, 99)
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 5, None, None, ctypes.byref(bad), ws, 1 << 30,
+                        None) == _lib.SC_EINVAL
+    big = _lib.sc_tune(33, -1)
+    assert lib.sc_carve(None, FAKE, 10, 10, 3, 30, 5, None, None, ctypes.byref(big), ws, 1 << 30,
+                        None) == _lib.SC_EUNSUPPORTED
+
+
+def test_dp_and_remove_and_transpose_validation(lib):
+    assert lib.sc_dp_seam(FAKE, 4, 4, FAKE, FAKE, None, FAKE, 8, None) == _lib.SC_ENOMEM
+    assert lib.sc_dp_seam(None, 4, 4, FAKE, FAKE, None, FAKE, 1 << 20, None) == _lib.SC_EINVAL
+    assert lib.sc_remove_seam(FAKE, 4, 0, 3, 12, FAKE, None) == _lib.SC_EINVAL
+    # overlapping transpose buffers
+    assert lib.sc_transpose_u8(FAKE, 4, 4, 3, 12, ctypes.c_void_p(0x1008), 12, None) == _lib.SC_EINVAL
+
+
+def test_batch_validation(lib):
+    jobs = (_lib.sc_job * 2)()
+    jobs[0] = _lib.sc_job(None, 0x1000, 10, 10, 3, 30, 5, None, None)
+    jobs[1] = _lib.sc_job(None, 0x2000, 10, 10, 3, 30, 0, None, None)  # bad target
+    info = _lib.sc_batch_info()
+    assert lib.sc_batch_prepare(jobs, 2, None, FAKE, 1 << 30, ctypes.byref(info)) == _lib.SC_EINVAL
+    assert b"job 1" in lib.sc_last_error()
+    assert lib.sc_batch_workspace_bytes(jobs, 2) > 0
+    assert lib.sc_batch_launch(ctypes.byref(info), FAKE, None) == _lib.SC_EINVAL  # nothing prepared
