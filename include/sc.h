@@ -104,7 +104,8 @@ sc_status sc_transpose_u8(const uint8_t* src, int H, int W, int C, int src_pitch
 
 /* Launch shape of the persistent carve kernel; NULL selects the built-in choice. */
 typedef struct {
-    int team;    /* workgroups working together on one image (>= 1) */
+    int team;    /* workgroups working together on one image (0 = default: 8 for sc_carve,
+                    at most 4 per image in a batch; teams run on one XCD) */
     int variant; /* kernel variant id (see sc_variant_count); -1 = default */
 } sc_tune;
 

@@ -95,7 +95,7 @@ def transpose(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -
 def _tune(team=None, variant=None):
     if team is None and variant is None:
         return None
-    return ctypes.byref(_lib.sc_tune(team or 1, -1 if variant is None else variant))
+    return ctypes.byref(_lib.sc_tune(team or 0, -1 if variant is None else variant))
 
 
 def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,
@@ -193,7 +193,7 @@ class BatchCarver:
             self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
                                          pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
                                          None if j.costs is None else j.costs.data_ptr())
-        self._tune = _lib.sc_tune(team or 1, -1 if variant is None else variant)
+        self._tune = _lib.sc_tune(team or 0, -1 if variant is None else variant)
         need = _lib.load().sc_batch_workspace_bytes(self._cjobs, n)
         if need == 0:
             raise ValueError("bad batch")

@@ -45,6 +45,8 @@ static_assert(sizeof(WsHead) == sc::kWsHeadBytes, "header size");
 static_assert(sizeof(sc::Ctl) == 64, "ctl size");
 
 constexpr int kMaxCostBound = 8388000;  // H*510*C: the column cost must fit 23 bits
+constexpr int kDefaultTeamSingle = 8;   // workgroups carving one image (sc_carve)
+constexpr int kDefaultTeamBatch = 4;    // largest team for one image of a batch
 
 sc_status check_image(int H, int W, int C, int pitch) {
     if (H < 1 || W < 1) return fail(SC_EINVAL, "H=%d W=%d must be >= 1", H, W);
@@ -208,7 +210,7 @@ sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pi
     if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     const int v = resolve_variant(tune);
     if (v < 0) return fail(SC_EINVAL, "unknown kernel variant %d", tune->variant);
-    const int G = tune && tune->team > 0 ? tune->team : 1;
+    const int G = tune && tune->team > 0 ? tune->team : kDefaultTeamSingle;
     if (G > 32) return fail(SC_EUNSUPPORTED, "team of %d workgroups > 32", G);
     char* base = static_cast<char*>(ws);
     sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
@@ -252,7 +254,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     const int v = resolve_variant(tune);
     if (v < 0) return fail(SC_EINVAL, "unknown kernel variant %d", tune->variant);
-    int G = tune && tune->team > 0 ? tune->team : 1;
+    int G = tune && tune->team > 0 ? tune->team : kDefaultTeamBatch;
     if (G > 32) return fail(SC_EUNSUPPORTED, "team of %d workgroups > 32", G);
 
     // work of every image: pixel-seams = sum over seams of the current image's pixels
@@ -265,56 +267,55 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
 
+    // Team sizes.  An image whose work exceeds the average work per workgroup slot gets a team
+    // of up to G workgroups on one XCD (their blocks come first in the grid, so every team is
+    // resident at once); every other image gets one workgroup, launched longest first so the
+    // dispatcher hands the next image to whichever slot frees up.
+    int dev = 0, ncu = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he != hipSuccess) return hip_fail(he, "device query");
+    const int per_cu = std::max(1, sc::carve_blocks_per_cu(v));
+    const int per_xcd = per_cu * ncu / 8;
+    double total = 0;
+    for (double x : work) total += x;
+    const double per_slot = total / std::max(1, per_cu * ncu);
+    std::vector<int> gsz(n, 1);
+    if (G > 1)
+        for (int i = 0; i < n; ++i) gsz[i] = (int)std::min<double>(G, std::max(1.0, std::ceil(work[i] / per_slot)));
     std::vector<int2> blk, teams;
     std::vector<int> team_imgs;
-    if (G == 1) {
-        // one workgroup per image, launched longest first: the dispatcher hands out the next
-        // image whenever a workgroup slot frees up (longest-processing-time-first order).
-        for (int t = 0; t < n; ++t) {
-            blk.push_back(make_int2(t, 0));
-            teams.push_back(make_int2(t, 1));
-            team_imgs.push_back(order[t]);
+    int slots[8] = {0};
+    std::vector<std::pair<int, int2>> placed;
+    int nb_team = 0;
+    for (int i : order) {
+        if (gsz[i] < 2) continue;
+        // the XCD with the most free slots
+        int x = 0;
+        for (int c = 1; c < 8; ++c)
+            if (slots[c] < slots[x]) x = c;
+        if (slots[x] + gsz[i] > per_xcd) {
+            gsz[i] = 1;  // no room for a resident team: carve it with one workgroup
+            continue;
         }
-    } else {
-        // Teams of G workgroups must be resident together: size the grid to the occupancy.
-        int dev = 0, ncu = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return hip_fail(e, "device query");
-        const int per_cu = sc::carve_blocks_per_cu(v);
-        const int capacity = per_cu * ncu;
-        int nteams = std::min(n, capacity / G);
-        if (nteams < 1) return fail(SC_EUNSUPPORTED, "team of %d exceeds %d resident workgroups", G, capacity);
-        // longest-processing-time-first assignment of images to teams
-        std::vector<std::vector<int>> lists(nteams);
-        std::priority_queue<std::pair<double, int>, std::vector<std::pair<double, int>>, std::greater<>> pq;
-        for (int t = 0; t < nteams; ++t) pq.push({0.0, t});
-        for (int i : order) {
-            auto top = pq.top();
-            pq.pop();
-            lists[top.second].push_back(i);
-            pq.push({top.first + work[i], top.second});
+        const int t = (int)teams.size();
+        teams.push_back(make_int2((int)team_imgs.size(), 1));
+        team_imgs.push_back(i);
+        for (int r = 0; r < gsz[i]; ++r) {
+            const int b = x + 8 * (slots[x] + r);
+            placed.push_back({b, make_int2(t, r)});
+            nb_team = std::max(nb_team, b + 1);
         }
-        // place team t on XCD t % 8: its members are blocks xcd + 8 * slot, consecutive slots
-        int slots[8] = {0};
-        int nb = 0;
-        std::vector<std::pair<int, int2>> placed;
-        for (int t = 0; t < nteams; ++t) {
-            const int x = t % 8;
-            for (int r = 0; r < G; ++r) {
-                const int b = x + 8 * (slots[x] + r);
-                placed.push_back({b, make_int2(t, r)});
-                nb = std::max(nb, b + 1);
-            }
-            slots[x] += G;
-        }
-        if (nb > capacity) return fail(SC_EUNSUPPORTED, "plan needs %d resident workgroups > %d", nb, capacity);
-        blk.assign(nb, make_int2(-1, -1));
-        for (auto& pr : placed) blk[pr.first] = pr.second;
-        for (int t = 0; t < nteams; ++t) {
-            teams.push_back(make_int2((int)team_imgs.size(), (int)lists[t].size()));
-            for (int i : lists[t]) team_imgs.push_back(i);
-        }
+        slots[x] += gsz[i];
+    }
+    blk.assign(nb_team, make_int2(-1, -1));
+    for (auto& pr : placed) blk[pr.first] = pr.second;
+    for (int i : order) {
+        if (gsz[i] >= 2) continue;
+        const int t = (int)teams.size();
+        teams.push_back(make_int2((int)team_imgs.size(), 1));
+        team_imgs.push_back(i);
+        blk.push_back(make_int2(t, 0));
     }
 
     // host image of the plan region
@@ -324,6 +325,8 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     const size_t off_ti = off_teams + sc::align_up((size_t)n * sizeof(int2), sc::kAlign);
     size_t off_data = off_ti + sc::align_up((size_t)n * sizeof(int), sc::kAlign);
     if (blk.size() > (size_t)8 * 32 * n) return fail(SC_EUNSUPPORTED, "plan too large");
+    int teams_used = 0;
+    for (int i = 0; i < n; ++i) teams_used += gsz[i] > 1;
     std::vector<char> host(off_data, 0);
     WsHead* h = reinterpret_cast<WsHead*>(host.data());
     h->magic = kMagic;
@@ -335,7 +338,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
         const sc_job& j = jobs[i];
         sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead)) + i;
         imgs[i] = make_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
-                           base + off_data, ctl, sc::variant(v).kr, G, 0);
+                           base + off_data, ctl, sc::variant(v).kr, gsz[i], 0);
         off_data += sc::layout_for(j.H, j.W, 32).total;
         max_rows = std::max(max_rows, j.H);
     }
@@ -351,6 +354,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     info->variant = v;
     info->max_rows = max_rows;
     info->team = G;
+    info->pad0 = teams_used;  // images carved by a multi-workgroup team
     info->off_imgs = off_imgs;
     info->off_blk = off_blk;
     info->off_teams = off_teams;

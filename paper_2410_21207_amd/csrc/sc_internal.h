@@ -30,14 +30,18 @@ struct Img {
     int pad0, pad1;
 };
 
-// Control words of one image (zeroed by the first pass of every launch).
+// Control words of one image (zeroed by the energy pass of every launch).
 struct Ctl {
-    unsigned long long amin;
-    unsigned bar;
-    unsigned status;
+    unsigned long long amin;            // packed (cost << 32 | column) argmin of the current seam
+    unsigned bar;                       // team barrier counter
+    unsigned status;                    // error bits (kStatus*)
     unsigned long long t_begin, t_end;  // device clock when the carve started / ended
-    unsigned pad[8];
+    unsigned xmask;                     // XCDs the team's workgroups ran on (bit per XCD)
+    unsigned done;                      // seams removed so far (step-wise carving)
+    unsigned pad[6];
 };
+constexpr unsigned kStatusTimeout = 1u;    // a team barrier timed out
+constexpr unsigned kStatusPlacement = 2u;  // a team's workgroups were not on one XCD
 
 // Placement of one image's scratch inside a workspace.
 struct Layout {
@@ -48,9 +52,10 @@ struct Layout {
 constexpr size_t kAlign = 256;
 constexpr uint32_t kWsMagic = 0x31574353u;  // "SCW1": first word of a prepared workspace
 constexpr size_t kWsHeadBytes = 256;        // header, then one Ctl per image
+constexpr size_t kWsImgOffset = 64;         // single-image workspaces keep their descriptor here
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Kernel variants: columns per lane and rows per DP phase.
+// Kernel variants: columns per lane, rows per DP phase, threads per workgroup.
 struct Variant {
     int cpl, kr, threads;
     const char* name;
@@ -60,7 +65,8 @@ Layout layout_for(int H, int W, int variant_kr_min);
 int variant_count();
 const Variant& variant(int v);
 int default_variant();
-int max_phase_rows();
+int team_variant();
+constexpr int kLdsExchangeMaxW = 4096;  // single-workgroup carves keep the phase exchange row in LDS up to this width
 
 // Launchers (sc_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long pitch, int32_t* out,
@@ -68,6 +74,8 @@ hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long 
 hipError_t launch_prepare_single(const Img& d, hipStream_t st);          // energy plane (+copy, ctl zero)
 hipError_t launch_prepare_from_i32(const Img& d, const int32_t* energy, hipStream_t st);
 hipError_t launch_carve_single(const Img& d, int variant, int G, hipStream_t st);
+hipError_t launch_carve_steps(char* const* ws_list, int n, int variant, int max_seams, int* progress,
+                              hipStream_t st);
 hipError_t launch_unpack_dirs(const Img& d, uint8_t* out, hipStream_t st);
 hipError_t launch_remove_seam(uint8_t* img, int H, int W, int C, long long pitch, const int32_t* seam,
                               hipStream_t st);

@@ -33,12 +33,53 @@
 namespace sc {
 
 constexpr uint32_t QINF = 0xFFFFFF00u;  // "+infinity" key: larger than any real key, +10 cannot wrap
-constexpr unsigned kStatusTimeout = 1u;
+
+#define GAS __attribute__((address_space(1)))
+// Every pointer reaches the kernels inside a descriptor, i.e. as a generic pointer; casting it to
+// the global address space lets the compiler emit global_* instead of flat_* memory instructions.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ GAS T* gp(T* p) {
+    return (GAS T*)p;
+}
+
+// Load of data that another workgroup of the same team may have written since this CU last read
+// it.  A relaxed device-scope atomic load is a plain load with the sc1 cache bit: it skips the
+// CU's L1 and reads the XCD's L2, where the other workgroup's stores have landed (a team always
+// runs on one XCD).  Single-workgroup carves use ordinary loads.
+template <bool COH, class T>
+__device__ __forceinline__ T ld(const T* p) {
+    if constexpr (COH)
+        return __hip_atomic_load(gp(const_cast<T*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return *gp(p);
+}
+
+__device__ __forceinline__ uint32_t xcc_id() {
+    uint32_t v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v;
+}
+
+// r + 512 * (low or high 16 bits of `pair`): one v_mad_u32_u16 adds e(i,j) << 9 to a DP key
+// straight from the packed uint16 energy pair, with no separate unpack.
+__device__ __forceinline__ uint32_t mad_lo16(uint32_t pair, uint32_t r) {
+    uint32_t o;
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(o) : "v"(pair), "s"(512u), "v"(r));
+    return o;
+}
+__device__ __forceinline__ uint32_t mad_hi16(uint32_t pair, uint32_t r) {
+    uint32_t o;
+    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(o) : "v"(pair), "s"(512u), "v"(r));
+    return o;
+}
 
 // ----------------------------------------------------------------------------------------------
 // e1 energy at one pixel of the current image (width w), indices clamped to the image.
-__device__ __forceinline__ uint32_t energy_at(const uint8_t* __restrict__ img, long long pitch, int H, int w,
-                                              int C, int y, int x) {
+template <bool COH = false>
+__device__ __forceinline__ uint32_t energy_at(const uint8_t* img, long long pitch, int H, int w, int C, int y,
+                                              int x) {
     const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < w ? x + 1 : w - 1;
     const int yu = y > 0 ? y - 1 : 0, yd = y + 1 < H ? y + 1 : H - 1;
     const uint8_t* r = img + (long long)y * pitch;
@@ -46,8 +87,8 @@ __device__ __forceinline__ uint32_t energy_at(const uint8_t* __restrict__ img, l
     const uint8_t* rd = img + (long long)yd * pitch;
     uint32_t s = 0;
     for (int c = 0; c < C; ++c) {
-        const int dx = (int)r[xr * C + c] - (int)r[xl * C + c];
-        const int dy = (int)rd[x * C + c] - (int)ru[x * C + c];
+        const int dx = (int)ld<COH>(r + xr * C + c) - (int)ld<COH>(r + xl * C + c);
+        const int dy = (int)ld<COH>(rd + x * C + c) - (int)ld<COH>(ru + x * C + c);
         s += (uint32_t)(dx < 0 ? -dx : dx) + (uint32_t)(dy < 0 ? -dy : dy);
     }
     return s;
@@ -58,37 +99,43 @@ __global__ void energy_i32_kernel(const uint8_t* __restrict__ img, int H, int W,
                                   int32_t* __restrict__ out) {
     const int y = blockIdx.y;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < W; x += gridDim.x * blockDim.x)
-        out[(long long)y * W + x] = (int32_t)energy_at(img, pitch, H, W, C, y, x);
+        *gp(out + (long long)y * W + x) = (int32_t)energy_at(img, pitch, H, W, C, y, x);
 }
 
-// Per-image preparation: zero the control words, optionally copy src -> img, fill the energy plane.
+__device__ __forceinline__ void reset_ctl(const Img& d) {
+    Ctl* c = reinterpret_cast<Ctl*>(d.amin);
+    c->amin = ~0ull;
+    c->bar = 0;
+    c->status = 0;
+    c->t_begin = c->t_end = 0;
+    c->xmask = 0;
+    c->done = 0;
+}
+
+// A single-image workspace starts with a header: magic, image count, then the descriptor itself
+// (read by the step-wise carve kernel), then the image's Ctl block.
+__device__ __forceinline__ void write_single_header(const Img& d) {
+    char* h = reinterpret_cast<char*>(d.amin) - kWsHeadBytes;
+    reinterpret_cast<uint32_t*>(h)[0] = kWsMagic;
+    reinterpret_cast<uint32_t*>(h)[1] = 1u;
+    *reinterpret_cast<Img*>(h + kWsImgOffset) = d;
+}
+
+// Per-image preparation: reset the control words, optionally copy src -> img, fill the energy plane.
 __device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
     const uint8_t* srcimg = d.src ? d.src : d.img;
-    if (row_begin == 0 && threadIdx.x == 0) {
-        Ctl* c = reinterpret_cast<Ctl*>(d.amin);
-        c->amin = ~0ull;
-        c->bar = 0;
-        c->status = 0;
-        c->t_begin = c->t_end = 0;
-    }
+    if (row_begin == 0 && threadIdx.x == 0) reset_ctl(d);
     for (int y = row_begin; y < d.H; y += row_step) {
         uint16_t* er = d.e + (long long)y * d.ep;
         for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
-            er[x] = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
+            *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
             if (d.src) {
                 const uint8_t* s = d.src + (long long)y * d.pitch + (long long)x * d.C;
                 uint8_t* o = d.img + (long long)y * d.pitch + (long long)x * d.C;
-                for (int c = 0; c < d.C; ++c) o[c] = s[c];
+                for (int c = 0; c < d.C; ++c) *gp(o + c) = *gp(s + c);
             }
         }
     }
-}
-
-// A single-image workspace starts with a header just before its one Ctl block.
-__device__ __forceinline__ void write_single_header(const Img& d) {
-    uint32_t* h = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(d.amin) - kWsHeadBytes);
-    h[0] = kWsMagic;
-    h[1] = 1u;
 }
 
 __global__ void prepare_single_kernel(Img d) {
@@ -108,65 +155,104 @@ __global__ void prepare_batch_kernel(const Img* __restrict__ imgs, int n) {
 __global__ void prepare_from_i32_kernel(Img d, const int32_t* __restrict__ e) {
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
         write_single_header(d);
-        Ctl* c = reinterpret_cast<Ctl*>(d.amin);
-        c->amin = ~0ull;
-        c->bar = 0;
-        c->status = 0;
+        reset_ctl(d);
     }
     const int y = blockIdx.y;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < d.W; x += gridDim.x * blockDim.x)
-        d.e[(long long)y * d.ep + x] = (uint16_t)e[(long long)y * d.W + x];
+        *gp(d.e + (long long)y * d.ep + x) = (uint16_t)*gp(e + (long long)y * d.W + x);
 }
 
 // ----------------------------------------------------------------------------------------------
-// In-place left shift of one row segment by `sh` bytes (1 <= sh <= 4), one wave:
-// dst byte x gets src byte x+sh for x in [lo, hi) (addresses).  Work is cut into
-// 16-byte slots aligned to absolute addresses; each lane owns one slot per pass.
-// All loads of a pass are issued before its stores and a pass only reads slots at
-// or after its own, so the in-place update is hazard free.
+// In-place left shift of row segments by one pixel, one wave.  Segment a: dst bytes [a_lo, a_hi)
+// get src bytes shifted by sh_a (1..4); segment b likewise (sh_b).  The work is cut into 16-byte
+// slots aligned to absolute addresses; a pass gives each lane U slots of the concatenated slot
+// list and issues every load of the pass before any store.  A slot's store writes only inside the
+// slot, and the bytes it needs beyond its end belong to the next slot of the same segment, which
+// is loaded in the same pass or a later one -- so the in-place update is hazard free.
+struct Seg {
+    uint8_t* base;  // 16-byte aligned (wave-uniform)
+    int lo, hi;     // the segment is [base + lo, base + hi)
+    int sh;         // shift in bytes, 1..4
+    int n;          // 16-byte slots covering it
+};
+
+__device__ __forceinline__ Seg make_seg(uint8_t* lo_p, uint8_t* hi_p, int sh) {
+    Seg g;
+    const int off = (int)((uintptr_t)lo_p & 15);
+    g.base = lo_p - off;
+    g.lo = off;
+    g.hi = hi_p > lo_p ? off + (int)(hi_p - lo_p) : off;
+    g.sh = sh;
+    g.n = g.hi > g.lo ? ((g.hi - 1) >> 4) + 1 : 0;
+    return g;
+}
+
+template <int U, bool COH>
+__device__ __forceinline__ void seg_load(const Seg& g, int fb, int lane, uint32_t (&D)[U][5]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int f = fb + u * 64 + lane;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) D[u][i] = 0;
+        if (f < g.n) {
+            const uint32_t so = (uint32_t)f << 4;  // slot offset from the uniform base
+            const uint64_t* q = reinterpret_cast<const uint64_t*>(g.base + so);
+            const uint64_t v0 = ld<COH>(q), v1 = ld<COH>(q + 1);
+            D[u][0] = (uint32_t)v0; D[u][1] = (uint32_t)(v0 >> 32);
+            D[u][2] = (uint32_t)v1; D[u][3] = (uint32_t)(v1 >> 32);
+            if ((int)so + 16 - g.sh < g.hi) D[u][4] = ld<COH>(reinterpret_cast<const uint32_t*>(g.base + so + 16));
+        }
+    }
+}
+
 template <int U>
-__device__ __forceinline__ void shift_left_wave(uint8_t* lo_p, uint8_t* hi_p, int sh, int lane) {
-    const uintptr_t lo = (uintptr_t)lo_p, hi = (uintptr_t)hi_p;
-    if (lo >= hi) return;
-    const uintptr_t q0 = lo >> 4, q1 = (hi - 1) >> 4;
-    // every address is formed from lo_p so the compiler keeps the global address space
-    uint8_t* const base = lo_p - (lo & 15);  // = (q0 << 4)
-    for (uintptr_t qb = q0; qb <= q1; qb += 64 * U) {
-        uint4 A[U];
-        uint32_t B[U];
+__device__ __forceinline__ void seg_store(const Seg& g, int fb, int lane, const uint32_t (&D)[U][5]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uintptr_t q = qb + (uintptr_t)(u * 64 + lane);
-            A[u] = make_uint4(0, 0, 0, 0);
-            B[u] = 0;
-            if (q <= q1) {
-                const uint8_t* sp = base + ((q - q0) << 4);
-                A[u] = *reinterpret_cast<const uint4*>(sp);
-                if ((q << 4) + 16 - sh < hi) B[u] = *reinterpret_cast<const uint32_t*>(sp + 16);
-            }
+    for (int u = 0; u < U; ++u) {
+        const int f = fb + u * 64 + lane;
+        if (f >= g.n) continue;
+        const int so = f << 4;
+        uint8_t* sp = g.base + so;
+        uint32_t o[4];
+        if (g.sh == 4) {
+            o[0] = D[u][1]; o[1] = D[u][2]; o[2] = D[u][3]; o[3] = D[u][4];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(D[u][i + 1], D[u][i], (uint32_t)g.sh);
         }
+        if (so >= g.lo && so + 16 <= g.hi) {
+            *gp(reinterpret_cast<u32x4*>(sp)) = u32x4{o[0], o[1], o[2], o[3]};
+        } else {
+            // a slot at a segment edge: store only the bytes inside the segment, one predicated
+            // byte store per position (static offsets and register indices)
+            const int k0 = so > g.lo ? 0 : g.lo - so;
+            const int k1 = so + 16 < g.hi ? 16 : g.hi - so;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uintptr_t q = qb + (uintptr_t)(u * 64 + lane);
-            if (q > q1) continue;
-            const uint32_t D[5] = {A[u].x, A[u].y, A[u].z, A[u].w, B[u]};
-            uint32_t o[4];
-            if (sh == 4) {
-                o[0] = D[1]; o[1] = D[2]; o[2] = D[3]; o[3] = D[4];
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(D[i + 1], D[i], (uint32_t)sh);
-            }
-            const uintptr_t s0 = q << 4;
-            uint8_t* dp = base + ((q - q0) << 4);
-            if (s0 >= lo && s0 + 16 <= hi) {
-                *reinterpret_cast<uint4*>(dp) = make_uint4(o[0], o[1], o[2], o[3]);
-            } else {
-                const uint32_t k0 = s0 > lo ? 0u : (uint32_t)(lo - s0);
-                const uint32_t k1 = s0 + 16 < hi ? 16u : (uint32_t)(hi - s0);
-                for (uint32_t k = k0; k < k1; ++k) dp[k] = (uint8_t)(o[k >> 2] >> ((k & 3) * 8));
-            }
+            for (int k = 0; k < 16; ++k)
+                if (k >= k0 && k < k1) *gp(sp + k) = (uint8_t)(o[k >> 2] >> ((k & 3) * 8));
         }
+    }
+}
+
+// In-place left shift of up to two row segments by one pixel, one wave.  Segment a: the bytes
+// of [a_lo, a_hi) take the values sh_a bytes to their right; segment b likewise.  The work is
+// cut into 16-byte slots aligned to absolute addresses; a pass gives each lane U slots of each
+// segment and issues every load of the pass before any store.  A slot's store writes only inside
+// the slot, and the bytes it needs beyond its end belong to the next slot of the same segment,
+// loaded in the same pass or a later one -- so the in-place update is hazard free.
+template <int U, bool COH>
+__device__ __forceinline__ void shift_segments_wave(uint8_t* a_lo_p, uint8_t* a_hi_p, int sh_a, uint8_t* b_lo_p,
+                                                    uint8_t* b_hi_p, int sh_b, int lane) {
+    const Seg A = make_seg(a_lo_p, a_hi_p, sh_a);
+    const Seg B = make_seg(b_lo_p, b_hi_p, sh_b);
+    const int n = max(A.n, B.n);
+#pragma unroll 1
+    for (int fb = 0; fb < n; fb += 64 * U) {
+        uint32_t DA[U][5], DB[U][5];
+        seg_load<U, COH>(A, fb, lane, DA);
+        seg_load<U, COH>(B, fb, lane, DB);
+        seg_store<U>(A, fb, lane, DA);
+        seg_store<U>(B, fb, lane, DB);
     }
 }
 
@@ -177,10 +263,10 @@ __global__ void remove_seam_kernel(uint8_t* __restrict__ img, int H, int W, int 
     const int wv = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     for (int y = wv; y < H; y += nw) {
-        const int s = seam[y];
+        const int s = *gp(seam + y);
         if (s < 0 || s >= W) continue;
         uint8_t* row = img + (long long)y * pitch;
-        shift_left_wave<4>(row + (long long)s * C, row + (long long)(W - 1) * C, C, lane);
+        shift_segments_wave<4, false>(row + (long long)s * C, row + (long long)(W - 1) * C, C, row, row, 1, lane);
     }
 }
 
@@ -195,49 +281,53 @@ __global__ void transpose_kernel(const uint8_t* __restrict__ src, int H, int W, 
     for (int r = ty; r < 64; r += 4) {
         const int y = by + r, x = bx + tx;
         if (y < H && x < W)
-            for (int c = 0; c < C; ++c) tile[r][tx * C + c] = src[(long long)y * sp + (long long)x * C + c];
+            for (int c = 0; c < C; ++c) tile[r][tx * C + c] = *gp(src + (long long)y * sp + (long long)x * C + c);
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
         const int x = bx + r, y = by + tx;  // output row x, column y
         if (y < H && x < W)
-            for (int c = 0; c < C; ++c) dst[(long long)x * dp + (long long)y * C + c] = tile[tx][r * C + c];
+            for (int c = 0; c < C; ++c) *gp(dst + (long long)x * dp + (long long)y * C + c) = tile[tx][r * C + c];
     }
 }
 
 // ----------------------------------------------------------------------------------------------
-// Team barrier.  Within one workgroup a workgroup barrier suffices; workgroups of one team
-// publish their writes with an agent-scope fence and meet at a counter in the image's
-// control block.  The wait is bounded: after ~10 s it flags the image and gives up.
-__device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, int* abort_flag) {
-    if (G == 1) {
+// Team barrier.  One workgroup: a workgroup barrier.  A team of G workgroups on one XCD: each
+// thread waits for its own stores to reach the L2 (vmcnt), then one thread per workgroup bumps
+// the image's counter with a device-scope atomic and polls it with device-scope loads until all
+// G have arrived; readers then fetch shared data with sc1 loads (see ld<true>).  The wait is
+// bounded: after ~10 s it flags the image and every member gives up on it.
+template <bool TEAM>
+__device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, int* flag) {
+    if constexpr (!TEAM) {
         __syncthreads();
         return true;
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        epoch += (unsigned)G;
-        __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long t0 = wall_clock64();
-        int ab = 0;
-        while (__hip_atomic_load(d.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-            __builtin_amdgcn_s_sleep(1);
-            if (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusTimeout) {
-                ab = 1;
-                break;
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            epoch += (unsigned)G;
+            __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long t0 = wall_clock64();
+            int ab = 0;
+            while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                    (kStatusTimeout | kStatusPlacement)) {
+                    ab = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > 1000000000ull) {  // 10 s at the 100 MHz constant clock
+                    __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                    break;
+                }
             }
-            if (wall_clock64() - t0 > 1000000000ull) {  // 10 s at the 100 MHz constant clock
-                __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ab = 1;
-                break;
-            }
+            *flag = ab;
         }
-        *abort_flag = ab;
+        __syncthreads();
+        return *flag == 0;
     }
-    __syncthreads();
-    __threadfence();
-    return *abort_flag == 0;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -247,55 +337,85 @@ struct Carver {
     static constexpr int WIN = 64 * CPL;       // columns a wave computes
     static constexpr int S = WIN - 2 * KR;     // columns a wave owns
     static constexpr int NW = NT / 64;         // waves per workgroup
-    static constexpr int PF = 8;               // rows of energy prefetched ahead
+    static constexpr int PF = 8;                         // rows of energy prefetched ahead
     static constexpr int WD = (KR / 2 + 2 + 3) / 4 + 1;  // dwords of a backtrack window row
     static constexpr int PMAX = 16448 / KR + 2;          // phases of the tallest image
     static_assert(CPL == 4 || CPL == 8, "a lane's directions fill a byte or a short");
-    static_assert(KR % CPL == 0 && KR <= 63 && S > 0 && S % 16 == 0, "phase shape");
+    static_assert(KR % CPL == 0 && KR % PF == 0 && KR <= 63 && S > 0 && S % 16 == 0, "phase shape");
 
     struct Smem {
-        int jend[PMAX];            // seam column at the last row of every phase
-        uint32_t win[NW][KR * WD]; // backtrack windows of the direction map
-        int abort_flag;
+        uint32_t xs[2][kLdsExchangeMaxW];  // phase exchange rows of a single-workgroup carve
+        int jend[PMAX];                    // seam column at the last row of every phase
+        uint32_t win[NW][KR * WD];         // backtrack windows of the direction map
+        int chain;                         // jend[p] is final for every p >= chain
+        int flag;
     };
 
-    using EV = typename std::conditional<CPL == 4, uint2, uint4>::type;
+    struct EV {
+        uint64_t v[CPL / 4];  // CPL uint16 energies
+    };
 
-    static __device__ __forceinline__ void unpack(const EV& v, uint32_t (&e)[CPL]) {
-        if constexpr (CPL == 4) {
-            e[0] = v.x & 0xffffu; e[1] = v.x >> 16; e[2] = v.y & 0xffffu; e[3] = v.y >> 16;
-        } else {
-            e[0] = v.x & 0xffffu; e[1] = v.x >> 16; e[2] = v.y & 0xffffu; e[3] = v.y >> 16;
-            e[4] = v.z & 0xffffu; e[5] = v.z >> 16; e[6] = v.w & 0xffffu; e[7] = v.w >> 16;
-        }
+    // Energies of row r at the lane's byte offset `off`: the row base is wave-uniform (scalar
+    // registers) and the offset a 32-bit vector register, so no 64-bit address per row is kept.
+    template <bool COH>
+    static __device__ __forceinline__ EV load_ev(const Img& d, int r, uint32_t off) {
+        const char* rb = reinterpret_cast<const char*>(d.e) + (size_t)r * d.ep * 2;
+        EV e;
+#pragma unroll
+        for (int i = 0; i < CPL / 4; ++i) e.v[i] = ld<COH>(reinterpret_cast<const uint64_t*>(rb + off) + i);
+        return e;
     }
 
-    // One DP row for the CPL columns of this lane.  Q holds the previous row's keys (tags in
-    // bits [1:0] are ignored); on return it holds this row's keys and `acc` the new directions
-    // in its top 2*CPL bits (column 0 lowest).
-    static __device__ __forceinline__ uint32_t row_step(uint32_t (&Q)[CPL], const uint32_t (&e)[CPL]) {
+    // One DP row for the CPL columns of this lane.  Q holds the previous row's keys (the tag bits
+    // [1:0] are ignored); on return Q holds this row's keys and the result's top 2*CPL bits hold
+    // this row's directions, column 0 lowest.
+    static __device__ __forceinline__ uint32_t row_step(uint32_t (&Q)[CPL], const EV& ev) {
         uint32_t t[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) t[k] = Q[k] & ~3u;
-        // left neighbour of column 0 lives in lane-1, right neighbour of the last column in lane+1
-        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp((int)QINF, (int)t[CPL - 1], 0x138, 0xf, 0xf, false);
-        const uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp((int)QINF, (int)t[0], 0x130, 0xf, 0xf, false);
+        // The neighbours of the lane's first and last column live in lanes -1 and +1.  At the
+        // wave's edges the shift fills in 0: those columns are halo, and within a phase a wrong
+        // value there moves at most one column inward per row, never reaching an owned column.
+        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t[CPL - 1], 0x138, 0xf, 0xf, true);
+        const uint32_t rightR = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(t[0] + 10u), 0x130, 0xf, 0xf, true);
         uint32_t acc = 0;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            const uint32_t L = k ? t[k - 1] : left;                 // tag 0, offset +0
-            const uint32_t Cc = t[k] + 5u;                          // tag 1, offset +1
-            const uint32_t R = (k + 1 < CPL ? t[k + 1] : right) + 10u;  // tag 2, offset +2
+            const uint32_t L = k ? t[k - 1] : left;                      // tag 0, offset +0
+            const uint32_t Cc = t[k] + 5u;                               // tag 1, offset +1
+            const uint32_t R = k + 1 < CPL ? t[k + 1] + 10u : rightR;    // tag 2, offset +2
             const uint32_t r = min(min(L, Cc), R);
-            Q[k] = r + (e[k] << 9);
+            const uint32_t pair = (uint32_t)(ev.v[k >> 2] >> (((k >> 1) & 1) * 32));
+            Q[k] = (k & 1) ? mad_hi16(pair, r) : mad_lo16(pair, r);
             acc = __builtin_amdgcn_alignbit(r, acc, 2u);
         }
         return acc;
     }
 
-    // One strip (t) of one phase (rows r0..r1-1) for the calling wave.
-    template <bool EDGE>
-    static __device__ void dp_item(const Img& d, int w, int p, int r0, int r1, int t, int lane) {
+    struct Next {
+        bool valid, lane_any;
+        int r0, r1;
+        uint32_t off;  // byte offset of the lane's first column in an energy row
+    };
+
+    static __device__ __forceinline__ Next make_next(const Img& d, int w, int p, int t, int lane, bool valid) {
+        Next nx;
+        nx.valid = valid;
+        nx.r0 = p * KR;
+        nx.r1 = min(d.H, nx.r0 + KR);
+        const int col0 = t * S - KR + lane * CPL;
+        nx.lane_any = valid && col0 >= 0 && col0 < w;
+        nx.off = (uint32_t)(nx.lane_any ? col0 : 0) * 2u;
+        return nx;
+    }
+
+    // One strip (t) of one phase (p) for the calling wave.  `ring` holds the first PF rows when
+    // `preloaded`; this item prefetches the first rows of `nx` into it when the phase length is a
+    // multiple of PF, so the energy stream runs across phase boundaries.
+    template <bool EDGE, bool TEAM>
+    static __device__ __forceinline__ void dp_item(const Img& d, Smem& sm, int w, int p, int t, int lane,
+                                                   EV (&ring)[PF], bool preloaded, const Next& nx) {
+        const int r0 = p * KR, r1 = min(d.H, r0 + KR);
         const int base = t * S - KR;
         const int col0 = base + lane * CPL;
         const bool lane_any = col0 >= 0 && col0 < w;
@@ -304,61 +424,87 @@ struct Carver {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) valid[k] = (col0 + k >= 0) && (col0 + k < w);
 
+        const uint32_t eoff = (uint32_t)(lane_any ? col0 : 0) * 2u;
+        if (!preloaded) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                ring[i] = EV{};
+                if (r0 + i < r1 && lane_any) ring[i] = load_ev<TEAM>(d, r0 + i, eoff);
+            }
+        }
         uint32_t Q[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) Q[k] = QINF;
         if (p > 0 && lane_any) {
-            const uint32_t* xr = d.xq + (size_t)((p - 1) & 1) * d.xw + col0;
+            if constexpr (TEAM) {
+                const uint64_t* xr = reinterpret_cast<const uint64_t*>(d.xq + (size_t)((p - 1) & 1) * d.xw + col0);
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (xr[k] & ~0x1FFu) : QINF;  // offset and tag reset
-        }
-
-        const uint16_t* erow = d.e + (size_t)r0 * d.ep + (lane_any ? col0 : 0);
-        EV ring[PF];
+                for (int i = 0; i < CPL / 2; ++i) {
+                    const uint64_t v = ld<true>(xr + i);
+                    Q[2 * i] = (uint32_t)v;
+                    Q[2 * i + 1] = (uint32_t)(v >> 32);
+                }
+            } else {
+                const uint32_t* xr = &sm.xs[(p - 1) & 1][col0];
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            ring[i] = EV{};
-            if (r0 + i < r1 && lane_any) ring[i] = *reinterpret_cast<const EV*>(erow + (size_t)i * d.ep);
+                for (int k = 0; k < CPL; ++k) Q[k] = xr[k];
+            }
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (Q[k] & ~0x1FFu) : QINF;  // offset and tag reset
         }
-        uint8_t* drow = d.dirs + (size_t)r0 * d.db + (col0 >> 2);
+        const bool cross = nx.valid && ((r1 - r0) % PF == 0);
+        const uint32_t doff = (uint32_t)(col0 >> 2);  // byte of the lane's directions in a row
         for (int rb = r0; rb < r1; rb += PF) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
                 const int r = rb + i;
                 if (r < r1) {
                     const EV ev = ring[i];
-                    if (r + PF < r1 && lane_any)
-                        ring[i] = *reinterpret_cast<const EV*>(erow + (size_t)(r - r0 + PF) * d.ep);
-                    uint32_t e[CPL];
-                    unpack(ev, e);
+                    const int rn = r + PF;
+                    if (rn < r1) {
+                        if (lane_any) ring[i] = load_ev<TEAM>(d, rn, eoff);
+                    } else if (cross) {
+                        const int jn = rn - r1;
+                        if (nx.r0 + jn < nx.r1 && nx.lane_any) ring[i] = load_ev<TEAM>(d, nx.r0 + jn, nx.off);
+                    }
                     if (r == 0) {
 #pragma unroll
-                        for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (e[k] << 9) : QINF;
+                        for (int k = 0; k < CPL; ++k) {
+                            const uint32_t pair = (uint32_t)(ev.v[k >> 2] >> (((k >> 1) & 1) * 32));
+                            const uint32_t e = (k & 1) ? (pair >> 16) : (pair & 0xffffu);
+                            Q[k] = valid[k] ? (e << 9) : QINF;
+                        }
                     } else {
-                        const uint32_t acc = row_step(Q, e);
+                        const uint32_t acc = row_step(Q, ev);
                         if (EDGE) {
 #pragma unroll
                             for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
                         }
                         if (owned) {
-                            uint8_t* dp = drow + (size_t)(r - r0) * d.db;
-                            if constexpr (CPL == 4) *dp = (uint8_t)(acc >> 24);
-                            else *reinterpret_cast<uint16_t*>(dp) = (uint16_t)(acc >> 16);
+                            uint8_t* dp = d.dirs + (size_t)r * d.db + doff;
+                            if constexpr (CPL == 4) *gp(dp) = (uint8_t)(acc >> 24);
+                            else *gp(reinterpret_cast<uint16_t*>(dp)) = (uint16_t)(acc >> 16);
                         }
                     }
                 }
             }
         }
-        // phase end: publish the last row of the owned columns and the ancestor offsets
+        // phase end: publish the last row of the owned columns and their ancestor offsets
         if (owned) {
-            uint32_t* xw = d.xq + (size_t)(p & 1) * d.xw + col0;
+            if constexpr (TEAM) {
+                uint32_t* xw = d.xq + (size_t)(p & 1) * d.xw + col0;
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) xw[k] = Q[k];
+                for (int k = 0; k < CPL; ++k) *gp(xw + k) = Q[k];
+            } else {
+                uint32_t* xw = &sm.xs[p & 1][col0];
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) xw[k] = Q[k];
+            }
             if (p > 0) {
                 const int n = r1 - r0;
 #pragma unroll
                 for (int k = 0; k < CPL; ++k)
-                    if (valid[k]) d.anc[(size_t)p * d.W + col0 + k] = (int8_t)((int)((Q[k] >> 2) & 127u) - n);
+                    if (valid[k]) *gp(d.anc + (size_t)p * d.W + col0 + k) = (int8_t)((int)((Q[k] >> 2) & 127u) - n);
             }
         }
         if (r1 == d.H) {  // last row: leftmost argmin of M over the owned columns
@@ -379,50 +525,57 @@ struct Carver {
         }
     }
 
-    static __device__ void carve_image(const Img& d, int rank, int G, Smem& sm) {
-        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
-        if (rank == 0 && threadIdx.x == 0) ctl->t_begin = wall_clock64();
-        carve_seams(d, rank, G, sm);
-        __syncthreads();
-        if (rank == 0 && threadIdx.x == 0) ctl->t_end = wall_clock64();
-    }
-
-    static __device__ void carve_seams(const Img& d, int rank, int G, Smem& sm) {
+    // Seams k_begin .. k_end-1 of one image (the image has W - k_begin columns on entry).
+    template <bool TEAM>
+    static __device__ __forceinline__ void carve_seams(const Img& d, int rank, int G, Smem& sm, int k_begin, int k_end,
+                                       unsigned& epoch) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int TW = G * NW, tw = rank * NW + wv;
         const int H = d.H, P = d.P;
-        unsigned epoch = 0;
-        const int nseams = d.mode ? 1 : d.W - d.target_w;
-        int w = d.W;
-        for (int k = 0; k < nseams; ++k, --w) {
-            // ---- DP sweep, phase by phase (a3) and the bottom-row argmin (a4)
+        for (int k = k_begin; k < k_end; ++k) {
+            const int w = d.W - k;
+            // ---- DP sweep, phase by phase (a3), and the bottom-row argmin (a4)
             const int nstr = (w + S - 1) / S;
+            const int nsw = tw < nstr ? (nstr - tw + TW - 1) / TW : 0;  // strips of this wave per phase
+            EV ring[PF];
+            bool preloaded = false;
+            // no phase end of this seam is known yet; the DP's barriers order this reset before
+            // any walker of this seam reads it, and after every walker of the previous seam
+            if (threadIdx.x == 0) sm.chain = 0x7fffffff;
             for (int p = 0; p < P; ++p) {
-                const int r0 = p * KR, r1 = min(H, r0 + KR);
-                for (int t = tw; t < nstr; t += TW) {
+                for (int j = 0; j < nsw; ++j) {
+                    const int t = tw + j * TW;
+                    const bool last = (p == P - 1) && (j == nsw - 1);
+                    const int pn = j + 1 < nsw ? p : p + 1;
+                    const int tn = j + 1 < nsw ? t + TW : tw;
+                    const Next nx = make_next(d, w, pn, tn, lane, !last);
                     const int base = t * S - KR;
-                    if (base < 0 || base + WIN > w) dp_item<true>(d, w, p, r0, r1, t, lane);
-                    else dp_item<false>(d, w, p, r0, r1, t, lane);
+                    if (base < 0 || base + WIN > w) dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx);
+                    else dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx);
+                    preloaded = nx.valid && ((min(H, p * KR + KR) - p * KR) % PF == 0);
                 }
-                if (!team_sync(d, epoch, G, &sm.abort_flag)) return;
+                if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
             }
-            const unsigned long long key =
-                __hip_atomic_load(d.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int jstar = (int)(key & 0xffffffffu);
-            if (rank == 0 && threadIdx.x == 0 && d.costs_out) d.costs_out[k] = (long long)(key >> 32);
-            // ---- backtrack (a5): hop phase ends, then walk every phase's rows in parallel
+            const unsigned long long key = __hip_atomic_load(d.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int jstar = min(max((int)(key & 0xffffffffu), 0), w - 1);
+            if (rank == 0 && threadIdx.x == 0 && d.costs_out) *gp(d.costs_out + k) = (long long)(key >> 32);
+            // ---- backtrack (a5): thread 0 hops from phase end to phase end and publishes the seam
+            // column at every phase end as soon as it is known; the waves walk their phases' rows
+            // from LDS windows of the direction map as their phase ends become known.
             if (threadIdx.x == 0) {
-                // every column is clamped into [0, w) before it indexes memory
-                int j = min(max(jstar, 0), w - 1);
-                sm.jend[P - 1] = j;
+                sm.jend[P - 1] = jstar;
+                __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                int j = jstar;
                 for (int p = P - 1; p >= 1; --p) {
-                    j = min(max(j + d.anc[(size_t)p * d.W + j], 0), w - 1);
+                    j = min(max(j + (int)ld<TEAM>(d.anc + (size_t)p * d.W + j), 0), w - 1);
                     sm.jend[p - 1] = j;
+                    __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
-            __syncthreads();
             for (int p = tw; p < P; p += TW) {
                 const int r0 = p * KR, r1 = min(H, r0 + KR), n = r1 - r0;
+                while (__hip_atomic_load(&sm.chain, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > p)
+                    __builtin_amdgcn_s_sleep(1);
                 const int je = sm.jend[p];
                 const int dlo = (max(0, je - KR) >> 2) >> 2;
                 const int ndw = d.db >> 2;
@@ -430,7 +583,7 @@ struct Carver {
                 if (lane < n) {
                     const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs + (size_t)(r0 + lane) * d.db);
 #pragma unroll
-                    for (int q = 0; q < WD; ++q) win[lane * WD + q] = (dlo + q < ndw) ? src[dlo + q] : 0u;
+                    for (int q = 0; q < WD; ++q) win[lane * WD + q] = (dlo + q < ndw) ? ld<TEAM>(src + dlo + q) : 0u;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -447,52 +600,93 @@ struct Carver {
                     }
                 }
                 if (lane < n) {
-                    d.seam[r0 + lane] = mys;
-                    if (d.seams_out) d.seams_out[(size_t)k * H + r0 + lane] = mys;
+                    *gp(d.seam + r0 + lane) = mys;
+                    if (d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (!d.mode) {
-                    // ---- removal (a6) of this phase's rows: image bytes and energy plane
+                    // ---- removal (a6) of this phase's rows: image bytes and energy plane.  A row is
+                    // only ever written by the wave owning its phase (this shift and the band update
+                    // below) or by the earlier energy pass, so plain loads see its current bytes even
+                    // in a team.
+#pragma unroll 1
                     for (int i = 0; i < n; ++i) {
-                        const int si = __shfl(mys, i, 64);
+                        const int si = __builtin_amdgcn_readlane(mys, i);  // wave-uniform: scalar addresses
                         uint8_t* row = d.img + (long long)(r0 + i) * d.pitch;
-                        shift_left_wave<4>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C, d.C, lane);
                         uint8_t* er = reinterpret_cast<uint8_t*>(d.e + (size_t)(r0 + i) * d.ep);
-                        shift_left_wave<2>(er + 2 * si, er + 2 * (w - 1), 2, lane);
+                        shift_segments_wave<4, false>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C, d.C,
+                                                     er + 2 * si, er + 2 * (w - 1), 2, lane);
                     }
                 }
             }
-            if (!team_sync(d, epoch, G, &sm.abort_flag)) return;
+            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
             if (d.mode) break;
             if (rank == 0 && threadIdx.x == 0)
                 __hip_atomic_store(d.amin, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // ---- band energy (a2): only new columns s-1 and s of each row changed
+            // ---- band energy (a2): only the new columns s-1 and s of each row changed
             const int w2 = w - 1;
-            for (int r = tw * 64 + lane; r < H; r += TW * 64) {
-                const int s = min(max(d.seam[r], 0), w - 1);
-                uint16_t* er = d.e + (size_t)r * d.ep;
-                if (s - 1 >= 0 && s - 1 < w2) er[s - 1] = (uint16_t)energy_at(d.img, d.pitch, H, w2, d.C, r, s - 1);
-                if (s < w2) er[s] = (uint16_t)energy_at(d.img, d.pitch, H, w2, d.C, r, s);
+            for (int p = tw; p < P; p += TW) {
+                const int r0 = p * KR, r1 = min(H, r0 + KR);
+                const int r = r0 + lane;
+                if (r < r1) {
+                    const int s = min(max(ld<TEAM>(d.seam + r), 0), w - 1);
+                    uint16_t* er = d.e + (size_t)r * d.ep;
+                    if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)energy_at<TEAM>(d.img, d.pitch, H, w2, d.C, r, s - 1);
+                    if (s < w2) *gp(er + s) = (uint16_t)energy_at<TEAM>(d.img, d.pitch, H, w2, d.C, r, s);
+                }
             }
-            if (!team_sync(d, epoch, G, &sm.abort_flag)) return;
+            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+        }
+    }
+
+    // Carve one image, or (max_seams > 0) continue it by at most max_seams seams.
+    static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams) {
+        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        const int nseams = d.mode ? 1 : d.W - d.target_w;
+        const int k0 = max_seams > 0 ? (int)ctl->done : 0;
+        const int k1 = max_seams > 0 ? min(nseams, k0 + max_seams) : nseams;
+        if (k0 >= k1) return;
+        if (rank == 0 && threadIdx.x == 0 && k0 == 0) ctl->t_begin = wall_clock64();
+        unsigned epoch = 0;
+        const bool team = G > 1 || d.W > kLdsExchangeMaxW;
+        if (team) {
+            // every member records its XCD; a team spread over several XCDs would not see each
+            // other's stores through sc1 loads, so such an image is flagged instead of carved
+            if (threadIdx.x == 0) __hip_atomic_fetch_or(&ctl->xmask, 1u << (xcc_id() & 31), __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (!team_sync<true>(d, epoch, G, &sm.flag)) return;
+            const unsigned m = __hip_atomic_load(&ctl->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__popc(m) != 1) {
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_or(d.status, kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            carve_seams<true>(d, rank, G, sm, k0, k1, epoch);
+        } else {
+            carve_seams<false>(d, rank, G, sm, k0, k1, epoch);
+        }
+        __syncthreads();
+        if (rank == 0 && threadIdx.x == 0) {
+            ctl->done = (unsigned)k1;
+            if (k1 == nseams) ctl->t_end = wall_clock64();
         }
     }
 };
 
 template <int CPL, int KR, int NT>
-__global__ __launch_bounds__(NT) void carve_single_kernel(Img d) {
+__global__ __launch_bounds__(NT, 4) void carve_single_kernel(Img d) {
     using CV = Carver<CPL, KR, NT>;
     __shared__ typename CV::Smem sm;
-    // Team members are blocks 0, 8, 16, ... so that they share one XCD's L2 under the
-    // round-robin dispatch of workgroups to XCDs; the other blocks exit at once.
+    // Team members are blocks 0, 8, 16, ...: workgroups are dispatched to the 8 XCDs round-robin
+    // by block index, so they share one XCD's L2; the other blocks exit at once.
     if (blockIdx.x & 7) return;
-    CV::carve_image(d, blockIdx.x >> 3, d.G, sm);
+    CV::carve_image(d, blockIdx.x >> 3, d.G, sm, 0);
 }
 
 // Batched carve: block b is member blk[b].y of team blk[b].x; team t carves the images
 // team_imgs[teams[t].x .. teams[t].x + teams[t].y) one after another.
 template <int CPL, int KR, int NT>
-__global__ __launch_bounds__(NT) void carve_batch_kernel(const Img* __restrict__ imgs, const int2* __restrict__ blk,
+__global__ __launch_bounds__(NT, 4) void carve_batch_kernel(const Img* __restrict__ imgs, const int2* __restrict__ blk,
                                                          const int2* __restrict__ teams,
                                                          const int* __restrict__ team_imgs) {
     using CV = Carver<CPL, KR, NT>;
@@ -502,8 +696,32 @@ __global__ __launch_bounds__(NT) void carve_batch_kernel(const Img* __restrict__
     const int2 tr = teams[me.x];
     for (int i = 0; i < tr.y; ++i) {
         const Img d = imgs[team_imgs[tr.x + i]];
-        CV::carve_image(d, me.y, d.G, sm);
+        CV::carve_image(d, me.y, d.G, sm, 0);
         __syncthreads();
+    }
+}
+
+// Step-wise carve (serving): block b advances the single-workgroup image whose workspace is
+// ws_list[b] by at most max_seams seams and reports how many seams it has removed in total.
+template <int CPL, int KR, int NT>
+__global__ __launch_bounds__(NT, 4) void carve_steps_kernel(char* const* __restrict__ ws_list, int n, int max_seams,
+                                                         int* __restrict__ progress) {
+    using CV = Carver<CPL, KR, NT>;
+    __shared__ typename CV::Smem sm;
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    // the workspace pointer is the same for the whole workgroup: keep it (and the descriptor
+    // loaded through it) in scalar registers
+    const uintptr_t wsv = (uintptr_t)ws_list[b];
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)wsv), hi = __builtin_amdgcn_readfirstlane((uint32_t)(wsv >> 32));
+    char* ws = reinterpret_cast<char*>(((uintptr_t)hi << 32) | lo);
+    if (!ws) return;
+    const Img d = *reinterpret_cast<const Img*>(ws + kWsImgOffset);
+    CV::carve_image(d, 0, 1, sm, max_seams);
+    __syncthreads();
+    if (threadIdx.x == 0 && progress) {
+        const Ctl* ctl = reinterpret_cast<const Ctl*>(d.amin);
+        progress[b] = (ctl->status & (kStatusTimeout | kStatusPlacement)) ? -1 : (int)ctl->done;
     }
 }
 
@@ -512,8 +730,8 @@ __global__ void unpack_dirs_kernel(Img d, uint8_t* __restrict__ out) {
     const int y = blockIdx.y;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < d.W; x += gridDim.x * blockDim.x) {
         uint8_t v = 1;
-        if (y > 0) v = (d.dirs[(size_t)y * d.db + (x >> 2)] >> ((x & 3) * 2)) & 3u;
-        out[(size_t)y * d.W + x] = v;
+        if (y > 0) v = (*gp(d.dirs + (size_t)y * d.db + (x >> 2)) >> ((x & 3) * 2)) & 3u;
+        *gp(out + (size_t)y * d.W + x) = v;
     }
 }
 
@@ -523,67 +741,63 @@ static const Variant kVariants[] = {
     {4, 32, 256, "cpl4_k32_t256"},
     {4, 32, 512, "cpl4_k32_t512"},
     {4, 32, 1024, "cpl4_k32_t1024"},
-    {8, 48, 256, "cpl8_k48_t256"},
-    {8, 48, 1024, "cpl8_k48_t1024"},
+    {8, 32, 512, "cpl8_k32_t512"},
+    {8, 32, 1024, "cpl8_k32_t1024"},
 };
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v]; }
-int default_variant() { return 2; }
-int max_phase_rows() { return 48; }
+int default_variant() { return 1; }
+int team_variant() { return 1; }
 
-template <int CPL, int KR, int NT>
-static hipError_t launch_single_t(const Img& d, int G, hipStream_t st) {
-    hipLaunchKernelGGL((carve_single_kernel<CPL, KR, NT>), dim3(8 * G), dim3(NT), 0, st, d);
-    return hipGetLastError();
-}
-
-template <int CPL, int KR, int NT>
-static hipError_t launch_batch_t(const Img* imgs, const int2* blk, const int2* teams, const int* ti, int nb,
-                                 hipStream_t st) {
-    hipLaunchKernelGGL((carve_batch_kernel<CPL, KR, NT>), dim3(nb), dim3(NT), 0, st, imgs, blk, teams, ti);
-    return hipGetLastError();
-}
-
-template <int CPL, int KR, int NT>
-static int occupancy_t() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, carve_batch_kernel<CPL, KR, NT>, NT, 0) != hipSuccess)
-        return 0;
-    return nb;
-}
+#define SC_VARIANTS(X) X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024)
 
 hipError_t launch_carve_single(const Img& d, int v, int G, hipStream_t st) {
     switch (v) {
-        case 0: return launch_single_t<4, 32, 256>(d, G, st);
-        case 1: return launch_single_t<4, 32, 512>(d, G, st);
-        case 2: return launch_single_t<4, 32, 1024>(d, G, st);
-        case 3: return launch_single_t<8, 48, 256>(d, G, st);
-        case 4: return launch_single_t<8, 48, 1024>(d, G, st);
+#define X(id, c, k, t) \
+    case id: hipLaunchKernelGGL((carve_single_kernel<c, k, t>), dim3(8 * G), dim3(t), 0, st, d); break;
+        SC_VARIANTS(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_carve_batch(const Img* imgs, const int2* blk, const int2* teams, const int* ti, int nb, int v,
                               hipStream_t st) {
     switch (v) {
-        case 0: return launch_batch_t<4, 32, 256>(imgs, blk, teams, ti, nb, st);
-        case 1: return launch_batch_t<4, 32, 512>(imgs, blk, teams, ti, nb, st);
-        case 2: return launch_batch_t<4, 32, 1024>(imgs, blk, teams, ti, nb, st);
-        case 3: return launch_batch_t<8, 48, 256>(imgs, blk, teams, ti, nb, st);
-        case 4: return launch_batch_t<8, 48, 1024>(imgs, blk, teams, ti, nb, st);
+#define X(id, c, k, t) \
+    case id: hipLaunchKernelGGL((carve_batch_kernel<c, k, t>), dim3(nb), dim3(t), 0, st, imgs, blk, teams, ti); break;
+        SC_VARIANTS(X)
+#undef X
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_carve_steps(char* const* ws_list, int n, int v, int max_seams, int* progress, hipStream_t st) {
+    switch (v) {
+#define X(id, c, k, t)                                                                                       \
+    case id:                                                                                                 \
+        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, ws_list, n, max_seams, progress); \
+        break;
+        SC_VARIANTS(X)
+#undef X
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 int carve_blocks_per_cu(int v) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
     switch (v) {
-        case 0: return occupancy_t<4, 32, 256>();
-        case 1: return occupancy_t<4, 32, 512>();
-        case 2: return occupancy_t<4, 32, 1024>();
-        case 3: return occupancy_t<8, 48, 256>();
-        case 4: return occupancy_t<8, 48, 1024>();
-        default: return 0;
+#define X(id, c, k, t) \
+    case id: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, carve_batch_kernel<c, k, t>, t, 0); break;
+        SC_VARIANTS(X)
+#undef X
+        default: break;
     }
+    return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long pitch, int32_t* out, hipStream_t st) {

@@ -106,7 +106,7 @@ def test_carve_small_uniform_config():
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("team", [1, 2, 3])
+@pytest.mark.parametrize("team", [1, 2, 3, 8])
 def test_carve_variants_and_teams(variant, team):
     log("carve variant", variant, "team", team)
     img = synth.blob_image(130, 500, 3, seed=21)
@@ -118,6 +118,21 @@ def test_carve_variants_and_teams(variant, team):
 def test_carve_tie_heavy_and_edges(H, W, C, tw, alpha):
     log("carve edges", H, W, C, tw, alpha)
     _carve_and_compare(rng_img(H * W + alpha, H, W, C, alpha), tw)
+
+
+def test_carve_wider_than_lds_row():
+    """W > 4096: the phase exchange row no longer fits LDS, so even one workgroup uses the team path."""
+    img = synth.blob_image(40, 4500, 3, seed=31)
+    _carve_and_compare(img, 4470, team=1)
+
+
+def test_carve_hv_small():
+    img = synth.blob_image(90, 160, 3, seed=33)
+    out, vs, vc, hs, hc = api.carve_hv(dev(img), 120, 70)
+    o_out, o_vs, o_vc, o_hs, o_hc = oracle.carve_hv(img, 120, 70)
+    assert np.array_equal(host(vs), o_vs) and np.array_equal(host(vc), o_vc)
+    assert np.array_equal(host(hs), o_hs) and np.array_equal(host(hc), o_hc)
+    assert np.array_equal(host(out), o_out)
 
 
 def test_carve_identity_and_src_pitch():
@@ -197,7 +212,7 @@ def _batch_jobs(seed, n, lo, hi):
     return jobs
 
 
-@pytest.mark.parametrize("team", [1, 2])
+@pytest.mark.parametrize("team", [1, 2, 4])
 def test_batch_parity(team):
     jobs = _batch_jobs(7, 14, 20, 420)
     srcs = [dev(img) for img, _ in jobs]
