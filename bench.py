@@ -140,6 +140,10 @@ def main():
     lat_ms = [(te - t_first) * 1000.0 for _, te in times]
     run_ms = [(te - tb) * 1000.0 for tb, te in times]
 
+    # where the carve time goes: per-image stage clocks (first workgroup of each image)
+    stages = np.array(bc.stages())  # [n, 3] seconds
+    longest = int(np.argmax(run_ms))
+
     # algorithmic bytes of one carve launch, from the recorded seams
     res = bc.results()
     model_bytes = 0
@@ -180,6 +184,15 @@ def main():
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
                        "max": round(max(lat_ms), 2), "per_image_run_p50": round(pct(run_ms, 50), 2)},
         "energy_pass_ms": round(float(np.mean(energy_ms)), 3),
+        "stages_s_all_images": {"dp": round(float(stages[:, 0].sum()), 3),
+                                "backtrack_removal": round(float(stages[:, 1].sum()), 3),
+                                "band": round(float(stages[:, 2].sum()), 3)},
+        "longest_image": {"h": jobs[longest].h, "w": jobs[longest].w, "seams": jobs[longest].seams,
+                          "run_ms": round(run_ms[longest], 1),
+                          "dp_ms": round(float(stages[longest, 0]) * 1e3, 1),
+                          "backtrack_removal_ms": round(float(stages[longest, 1]) * 1e3, 1),
+                          "band_ms": round(float(stages[longest, 2]) * 1e3, 1)},
+        "teams": bc.info.pad0,
     }
 
     # graph replay of the same launch (informative)

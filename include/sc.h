@@ -182,6 +182,24 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
                          void* stream);
 
 /*
+ * Step-wise carving for a serving loop (continuous batching).  A slot table (device memory,
+ * sc_slot_table_bytes(n) bytes, caller-owned) holds one image per slot; each image keeps its own
+ * workspace (sc_workspace_bytes) and stays on the device between steps.
+ *   sc_slot_start  validates the job, writes its descriptor into slot `slot` of the table and
+ *                  enqueues its energy pass (copying job->src into job->img when src is given).
+ *   sc_slot_clear  empties slot `slot` (its workspace may then be reused).
+ *   sc_slots_step  advances every non-empty slot of the first n by at most max_seams seams in one
+ *                  launch (one workgroup per image) and writes progress[i] = seams removed so far
+ *                  (device int32; -1 = device error, -2 = empty slot).  A slot is done when
+ *                  progress equals W - target_w.  Calls that share a table must be ordered on
+ *                  one stream.
+ */
+size_t sc_slot_table_bytes(int n_slots);
+sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int slot, void* stream);
+sc_status sc_slot_clear(void* table, int slot, void* stream);
+sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream);
+
+/*
  * Device-side status of the images of a workspace (synchronous: waits for the
  * device).  flags[i] for image i (n = 1 for sc_carve/sc_dp_seam workspaces):
  * 0 = fine, bit 0 = a team barrier timed out (the results of that image are
@@ -195,6 +213,14 @@ int sc_read_status(const void* ws, uint32_t* flags, int max_n);
  * *hz receives that clock's rate.  Returns the number of images written, -1 on error.
  */
 int sc_read_times(const void* ws, uint64_t* t_begin, uint64_t* t_end, int max_n, double* hz);
+
+/*
+ * Device clock ticks (rate as in sc_read_times) each image's carve spent in its three stages,
+ * summed over its seams, as seen by its first workgroup (synchronous): stages[3*i + 0] the DP
+ * sweep with the bottom-row argmin, [3*i + 1] the backtrack and the removal, [3*i + 2] the band
+ * energy update.  Returns the number of images written, -1 on error.
+ */
+int sc_read_stages(const void* ws, uint64_t* stages, int max_n);
 
 #ifdef __cplusplus
 }

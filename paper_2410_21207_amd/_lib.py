@@ -53,6 +53,11 @@ SIGNATURES = {
     "sc_read_status": (I, [P, ctypes.POINTER(ctypes.c_uint32), I]),
     "sc_read_times": (I, [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), I,
                           ctypes.POINTER(ctypes.c_double)]),
+    "sc_read_stages": (I, [P, ctypes.POINTER(ctypes.c_uint64), I]),
+    "sc_slot_table_bytes": (Z, [I]),
+    "sc_slot_start": (I, [ctypes.POINTER(sc_job), P, Z, P, I, P]),
+    "sc_slot_clear": (I, [P, I, P]),
+    "sc_slots_step": (I, [P, I, I, P, P]),
 }
 
 _lib = None

@@ -14,7 +14,7 @@ import torch
 from . import _lib
 
 __all__ = ["energy", "dp_seam", "remove_seam", "transpose", "carve", "carve_hv", "workspace",
-           "BatchCarver", "variants", "read_status"]
+           "BatchCarver", "variants", "read_status", "read_times", "read_stages"]
 
 
 def _stream(stream=None):
@@ -157,6 +157,24 @@ def read_times(ws: torch.Tensor, n: int = 1):
     return [(tb[i] / hz.value, te[i] / hz.value) for i in range(got)]
 
 
+def read_stages(ws: torch.Tensor, n: int = 1):
+    """Seconds each image spent in (DP sweep, backtrack + removal, band update), summed over seams."""
+    out = (ctypes.c_uint64 * (3 * n))()
+    got = _lib.load().sc_read_stages(_ptr(ws), out, n)
+    if got < 0:
+        raise _lib.ScError(got, "sc_read_stages", _lib.load().sc_last_error().decode())
+    hz = read_times_hz(ws)
+    return [tuple(out[3 * i + j] / hz for j in range(3)) for i in range(got)]
+
+
+def read_times_hz(ws: torch.Tensor) -> float:
+    tb = (ctypes.c_uint64 * 1)()
+    te = (ctypes.c_uint64 * 1)()
+    hz = ctypes.c_double(0)
+    _lib.load().sc_read_times(_ptr(ws), tb, te, 1, ctypes.byref(hz))
+    return hz.value or 100e6
+
+
 @dataclass
 class _Job:
     src: torch.Tensor | None
@@ -218,6 +236,10 @@ class BatchCarver:
     def times(self):
         """Per-image (begin, end) of the last carve in seconds of the device clock."""
         return read_times(self.ws, len(self.jobs))
+
+    def stages(self):
+        """Per-image seconds in (DP sweep, backtrack + removal, band update) of the last carve."""
+        return read_stages(self.ws, len(self.jobs))
 
     def capture(self):
         """Capture launch() in a CUDA/HIP graph (requires every job to have a src)."""

@@ -461,3 +461,78 @@ extern "C" int sc_read_times(const void* ws, uint64_t* t_begin, uint64_t* t_end,
     ok();
     return n;
 }
+
+extern "C" int sc_read_stages(const void* ws, uint64_t* stages, int max_n) {
+    if (!ws || !stages || max_n < 1) {
+        fail(SC_EINVAL, "bad arguments");
+        return -1;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        fail(SC_EHIP, "device synchronize failed");
+        return -1;
+    }
+    WsHead h;
+    if (hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess || h.magic != kMagic || h.n < 1) {
+        fail(SC_EINVAL, "not a prepared workspace");
+        return -1;
+    }
+    const int n = std::min(h.n, max_n);
+    std::vector<sc::Ctl> c(n);
+    if (hipMemcpy(c.data(), static_cast<const char*>(ws) + sizeof(WsHead), n * sizeof(sc::Ctl),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+        fail(SC_EHIP, "stages copy failed");
+        return -1;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 3; ++j) stages[3 * i + j] = c[i].t_stage[j];
+    ok();
+    return n;
+}
+
+// ---------------------------------------------------------------------------------- serving slots
+constexpr size_t kSlotBytes = sizeof(sc::Img);  // the table is a device array of descriptors
+
+extern "C" size_t sc_slot_table_bytes(int n_slots) {
+    if (n_slots < 1) return 0;
+    return sc::align_up((size_t)n_slots * kSlotBytes, sc::kAlign);
+}
+
+extern "C" sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int slot,
+                                   void* stream) {
+    if (!job || !ws || !table || slot < 0) return fail(SC_EINVAL, "null pointer or negative slot");
+    sc_status s = check_image(job->H, job->W, job->C, job->pitch);
+    if (s != SC_OK) return s;
+    if (!job->img) return fail(SC_EINVAL, "null image");
+    if (job->target_w < 1 || job->target_w > job->W)
+        return fail(SC_EINVAL, "target_w=%d not in [1, W=%d]", job->target_w, job->W);
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const size_t need = sc_workspace_bytes(job->H, job->W, job->C);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    const int v = sc::default_variant();
+    char* base = static_cast<char*>(ws);
+    sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
+    sc::Img d = make_img(job->src, job->img, job->H, job->W, job->C, job->pitch, job->target_w, job->seams_out,
+                         job->costs_out, base + ctl_region(1), ctl, sc::variant(v).kr, 1, 0);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = sc::launch_prepare_single(d, st);
+    if (e == hipSuccess) e = sc::launch_slot_write(static_cast<sc::Img*>(table), slot, d, st);
+    if (e != hipSuccess) return hip_fail(e, "slot start");
+    return ok();
+}
+
+extern "C" sc_status sc_slot_clear(void* table, int slot, void* stream) {
+    if (!table || slot < 0) return fail(SC_EINVAL, "null table or negative slot");
+    sc::Img d;
+    memset(&d, 0, sizeof(d));
+    hipError_t e = sc::launch_slot_write(static_cast<sc::Img*>(table), slot, d, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "slot clear");
+    return ok();
+}
+
+extern "C" sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream) {
+    if (!table || n_slots < 1 || max_seams < 1) return fail(SC_EINVAL, "bad slot step arguments");
+    hipError_t e = sc::launch_carve_steps(static_cast<const sc::Img*>(table), n_slots, sc::default_variant(),
+                                          max_seams, progress, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "slot step");
+    return ok();
+}

@@ -38,7 +38,7 @@ struct Ctl {
     unsigned long long t_begin, t_end;  // device clock when the carve started / ended
     unsigned xmask;                     // XCDs the team's workgroups ran on (bit per XCD)
     unsigned done;                      // seams removed so far (step-wise carving)
-    unsigned pad[6];
+    unsigned long long t_stage[3];      // device clock spent in: DP sweep; backtrack + removal; band update
 };
 constexpr unsigned kStatusTimeout = 1u;    // a team barrier timed out
 constexpr unsigned kStatusPlacement = 2u;  // a team's workgroups were not on one XCD
@@ -74,8 +74,8 @@ hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long 
 hipError_t launch_prepare_single(const Img& d, hipStream_t st);          // energy plane (+copy, ctl zero)
 hipError_t launch_prepare_from_i32(const Img& d, const int32_t* energy, hipStream_t st);
 hipError_t launch_carve_single(const Img& d, int variant, int G, hipStream_t st);
-hipError_t launch_carve_steps(char* const* ws_list, int n, int variant, int max_seams, int* progress,
-                              hipStream_t st);
+hipError_t launch_carve_steps(const Img* table, int n, int variant, int max_seams, int* progress, hipStream_t st);
+hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st);
 hipError_t launch_unpack_dirs(const Img& d, uint8_t* out, hipStream_t st);
 hipError_t launch_remove_seam(uint8_t* img, int H, int W, int C, long long pitch, const int32_t* seam,
                               hipStream_t st);

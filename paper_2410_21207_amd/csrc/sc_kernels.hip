@@ -56,6 +56,19 @@ __device__ __forceinline__ T ld(const T* p) {
         return *gp(p);
 }
 
+// Raw buffer descriptors (gfx9 word 3).  A raw buffer access adds a wave-uniform byte offset
+// (scalar register) to a per-lane byte offset (vector register); only the per-lane part is
+// range checked, and an access whose per-lane offset is >= the descriptor's size is dropped
+// (loads return 0, stores write nothing).
+constexpr int kBufWord3 = 0x00020000;
+constexpr uint32_t kBufDrop = 0x80000000u;  // a per-lane offset beyond any descriptor used here
+typedef unsigned int v2u __attribute__((__vector_size__(8)));
+typedef unsigned int v4u __attribute__((__vector_size__(16)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufWord3);
+}
+
 __device__ __forceinline__ uint32_t xcc_id() {
     uint32_t v;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
@@ -110,6 +123,7 @@ __device__ __forceinline__ void reset_ctl(const Img& d) {
     c->t_begin = c->t_end = 0;
     c->xmask = 0;
     c->done = 0;
+    c->t_stage[0] = c->t_stage[1] = c->t_stage[2] = 0;
 }
 
 // A single-image workspace starts with a header: magic, image count, then the descriptor itself
@@ -355,14 +369,19 @@ struct Carver {
         uint64_t v[CPL / 4];  // CPL uint16 energies
     };
 
-    // Energies of row r at the lane's byte offset `off`: the row base is wave-uniform (scalar
-    // registers) and the offset a 32-bit vector register, so no 64-bit address per row is kept.
+    // Energies of row r (wave-uniform, a valid row) at the lane's byte offset `off` (a valid
+    // column): a buffer load with the row offset in a scalar register.  COH sets the sc1 bit.
     template <bool COH>
-    static __device__ __forceinline__ EV load_ev(const Img& d, int r, uint32_t off) {
-        const char* rb = reinterpret_cast<const char*>(d.e) + (size_t)r * d.ep * 2;
+    static __device__ __forceinline__ EV load_ev(__amdgpu_buffer_rsrc_t re, uint32_t row_bytes, int r, uint32_t off) {
         EV e;
-#pragma unroll
-        for (int i = 0; i < CPL / 4; ++i) e.v[i] = ld<COH>(reinterpret_cast<const uint64_t*>(rb + off) + i);
+        if constexpr (CPL == 4) {
+            const v2u v = __builtin_amdgcn_raw_buffer_load_b64(re, (int)off, (int)((uint32_t)r * row_bytes), COH ? 16 : 0);
+            e.v[0] = ((uint64_t)v[1] << 32) | v[0];
+        } else {
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(re, (int)off, (int)((uint32_t)r * row_bytes), COH ? 16 : 0);
+            e.v[0] = ((uint64_t)v[1] << 32) | v[0];
+            e.v[1] = ((uint64_t)v[3] << 32) | v[2];
+        }
         return e;
     }
 
@@ -401,7 +420,7 @@ struct Carver {
     static __device__ __forceinline__ Next make_next(const Img& d, int w, int p, int t, int lane, bool valid) {
         Next nx;
         nx.valid = valid;
-        nx.r0 = p * KR;
+        nx.r0 = __builtin_amdgcn_readfirstlane(p * KR);  // wave-uniform: a scalar buffer offset
         nx.r1 = min(d.H, nx.r0 + KR);
         const int col0 = t * S - KR + lane * CPL;
         nx.lane_any = valid && col0 >= 0 && col0 < w;
@@ -410,12 +429,14 @@ struct Carver {
     }
 
     // One strip (t) of one phase (p) for the calling wave.  `ring` holds the first PF rows when
-    // `preloaded`; this item prefetches the first rows of `nx` into it when the phase length is a
-    // multiple of PF, so the energy stream runs across phase boundaries.
+    // `preloaded`; when this phase's length is a multiple of PF, its last block of rows prefetches
+    // the first PF rows of the wave's next item `nx`, so the energy stream runs across phase
+    // boundaries.  The row loop has no lane-dependent branches: every load targets a valid row and
+    // column, and lanes that do not own their columns store their directions to a dropped offset.
     template <bool EDGE, bool TEAM>
     static __device__ __forceinline__ void dp_item(const Img& d, Smem& sm, int w, int p, int t, int lane,
                                                    EV (&ring)[PF], bool preloaded, const Next& nx) {
-        const int r0 = p * KR, r1 = min(d.H, r0 + KR);
+        const int r0 = __builtin_amdgcn_readfirstlane(p * KR), r1 = min(d.H, r0 + KR);
         const int base = t * S - KR;
         const int col0 = base + lane * CPL;
         const bool lane_any = col0 >= 0 && col0 < w;
@@ -424,71 +445,83 @@ struct Carver {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) valid[k] = (col0 + k >= 0) && (col0 + k < w);
 
-        const uint32_t eoff = (uint32_t)(lane_any ? col0 : 0) * 2u;
+        const uint32_t eoff = (uint32_t)(lane_any ? col0 : 0) * 2u;  // lanes off the image read column 0
+        const uint32_t erb = (uint32_t)d.ep * 2u;                       // bytes per energy row
+        const __amdgpu_buffer_rsrc_t re = make_rsrc(d.e, (uint32_t)d.H * erb);
+        const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)d.H * (uint32_t)d.db);
         if (!preloaded) {
 #pragma unroll
-            for (int i = 0; i < PF; ++i) {
-                ring[i] = EV{};
-                if (r0 + i < r1 && lane_any) ring[i] = load_ev<TEAM>(d, r0 + i, eoff);
-            }
+            for (int i = 0; i < PF; ++i) ring[i] = load_ev<TEAM>(re, erb, min(r0 + i, d.H - 1), eoff);
         }
+        // previous row's keys.  Phase 0 starts from a row of zeros: one ordinary DP step then gives
+        // M(0,j) = e(0,j) (its directions and offsets are never read).
         uint32_t Q[CPL];
+        if (p == 0) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) Q[k] = QINF;
-        if (p > 0 && lane_any) {
+            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? 0u : QINF;
+        } else {
+            const int cx = lane_any ? col0 : 0;
+            uint32_t x[CPL];
             if constexpr (TEAM) {
-                const uint64_t* xr = reinterpret_cast<const uint64_t*>(d.xq + (size_t)((p - 1) & 1) * d.xw + col0);
+                const uint64_t* xr = reinterpret_cast<const uint64_t*>(d.xq + (size_t)((p - 1) & 1) * d.xw + cx);
 #pragma unroll
                 for (int i = 0; i < CPL / 2; ++i) {
                     const uint64_t v = ld<true>(xr + i);
-                    Q[2 * i] = (uint32_t)v;
-                    Q[2 * i + 1] = (uint32_t)(v >> 32);
+                    x[2 * i] = (uint32_t)v;
+                    x[2 * i + 1] = (uint32_t)(v >> 32);
                 }
             } else {
-                const uint32_t* xr = &sm.xs[(p - 1) & 1][col0];
+                const uint32_t* xr = &sm.xs[(p - 1) & 1][cx];
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) Q[k] = xr[k];
+                for (int k = 0; k < CPL; ++k) x[k] = xr[k];
             }
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (Q[k] & ~0x1FFu) : QINF;  // offset and tag reset
+            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (x[k] & ~0x1FFu) : QINF;  // offset and tag reset
         }
         const bool cross = nx.valid && ((r1 - r0) % PF == 0);
-        const uint32_t doff = (uint32_t)(col0 >> 2);  // byte of the lane's directions in a row
-        for (int rb = r0; rb < r1; rb += PF) {
+        // byte of the lane's directions in a row; lanes that do not own their columns store to a
+        // dropped offset instead of branching around the store
+        const uint32_t doff = owned ? (uint32_t)(col0 >> 2) : kBufDrop;
+        const uint32_t db = (uint32_t)d.db;
+
+        auto step = [&](int r, const EV& ev) {
+            const uint32_t acc = row_step(Q, ev);
+            if (EDGE) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
+            }
+            if constexpr (CPL == 4)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(acc >> 24), rdir, (int)doff, (int)((uint32_t)r * db), 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(acc >> 16), rdir, (int)doff, (int)((uint32_t)r * db), 0);
+        };
+
+        int rb = r0;
+        // blocks whose prefetch targets stay inside this item
+        for (; rb + 2 * PF <= r1; rb += PF) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
-                const int r = rb + i;
-                if (r < r1) {
-                    const EV ev = ring[i];
-                    const int rn = r + PF;
-                    if (rn < r1) {
-                        if (lane_any) ring[i] = load_ev<TEAM>(d, rn, eoff);
-                    } else if (cross) {
-                        const int jn = rn - r1;
-                        if (nx.r0 + jn < nx.r1 && nx.lane_any) ring[i] = load_ev<TEAM>(d, nx.r0 + jn, nx.off);
-                    }
-                    if (r == 0) {
-#pragma unroll
-                        for (int k = 0; k < CPL; ++k) {
-                            const uint32_t pair = (uint32_t)(ev.v[k >> 2] >> (((k >> 1) & 1) * 32));
-                            const uint32_t e = (k & 1) ? (pair >> 16) : (pair & 0xffffu);
-                            Q[k] = valid[k] ? (e << 9) : QINF;
-                        }
-                    } else {
-                        const uint32_t acc = row_step(Q, ev);
-                        if (EDGE) {
-#pragma unroll
-                            for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
-                        }
-                        if (owned) {
-                            uint8_t* dp = d.dirs + (size_t)r * d.db + doff;
-                            if constexpr (CPL == 4) *gp(dp) = (uint8_t)(acc >> 24);
-                            else *gp(reinterpret_cast<uint16_t*>(dp)) = (uint16_t)(acc >> 16);
-                        }
-                    }
-                }
+                const EV ev = ring[i];
+                ring[i] = load_ev<TEAM>(re, erb, rb + i + PF, eoff);
+                step(rb + i, ev);
             }
         }
+        // the last full block prefetches the next item's first rows (or reloads its own, unused)
+        if (rb + PF <= r1) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                const EV ev = ring[i];
+                const int rn = cross ? min(nx.r0 + i, d.H - 1) : rb + i;
+                ring[i] = load_ev<TEAM>(re, erb, rn, cross ? nx.off : eoff);
+                step(rb + i, ev);
+            }
+            rb += PF;
+        }
+        // the rows of a partial last phase (the next item then loads its own first rows)
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+            if (rb + i < r1) step(rb + i, ring[i]);
+
         // phase end: publish the last row of the owned columns and their ancestor offsets
         if (owned) {
             if constexpr (TEAM) {
@@ -532,8 +565,12 @@ struct Carver {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int TW = G * NW, tw = rank * NW + wv;
         const int H = d.H, P = d.P;
+        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        const bool timer = rank == 0 && threadIdx.x == 0;  // one clock reader per image
+        unsigned long long tm0 = 0, tm1 = 0, tm2 = 0;
         for (int k = k_begin; k < k_end; ++k) {
             const int w = d.W - k;
+            if (timer) tm0 = wall_clock64();
             // ---- DP sweep, phase by phase (a3), and the bottom-row argmin (a4)
             const int nstr = (w + S - 1) / S;
             const int nsw = tw < nstr ? (nstr - tw + TW - 1) / TW : 0;  // strips of this wave per phase
@@ -556,6 +593,7 @@ struct Carver {
                 }
                 if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
             }
+            if (timer) tm1 = wall_clock64();
             const unsigned long long key = __hip_atomic_load(d.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int jstar = min(max((int)(key & 0xffffffffu), 0), w - 1);
             if (rank == 0 && threadIdx.x == 0 && d.costs_out) *gp(d.costs_out + k) = (long long)(key >> 32);
@@ -620,6 +658,7 @@ struct Carver {
                 }
             }
             if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+            if (timer) tm2 = wall_clock64();
             if (d.mode) break;
             if (rank == 0 && threadIdx.x == 0)
                 __hip_atomic_store(d.amin, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -636,6 +675,12 @@ struct Carver {
                 }
             }
             if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+            if (timer) {
+                const unsigned long long tm3 = wall_clock64();
+                ctl->t_stage[0] += tm1 - tm0;
+                ctl->t_stage[1] += tm2 - tm1;
+                ctl->t_stage[2] += tm3 - tm2;
+            }
         }
     }
 
@@ -701,22 +746,22 @@ __global__ __launch_bounds__(NT, 4) void carve_batch_kernel(const Img* __restric
     }
 }
 
-// Step-wise carve (serving): block b advances the single-workgroup image whose workspace is
-// ws_list[b] by at most max_seams seams and reports how many seams it has removed in total.
+// Step-wise carve (serving): block b advances the image in slot b of the slot table by at most
+// max_seams seams (one workgroup per image) and reports how many seams it has removed in total
+// (-1 on a device error, -2 for an empty slot).  The table is a device array of descriptors
+// written by slot_start_kernel, so each block reads its descriptor with scalar loads.
 template <int CPL, int KR, int NT>
-__global__ __launch_bounds__(NT, 4) void carve_steps_kernel(char* const* __restrict__ ws_list, int n, int max_seams,
-                                                         int* __restrict__ progress) {
+__global__ __launch_bounds__(NT, 4) void carve_steps_kernel(const Img* __restrict__ table, int n, int max_seams,
+                                                            int* __restrict__ progress) {
     using CV = Carver<CPL, KR, NT>;
     __shared__ typename CV::Smem sm;
     const int b = blockIdx.x;
     if (b >= n) return;
-    // the workspace pointer is the same for the whole workgroup: keep it (and the descriptor
-    // loaded through it) in scalar registers
-    const uintptr_t wsv = (uintptr_t)ws_list[b];
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)wsv), hi = __builtin_amdgcn_readfirstlane((uint32_t)(wsv >> 32));
-    char* ws = reinterpret_cast<char*>(((uintptr_t)hi << 32) | lo);
-    if (!ws) return;
-    const Img d = *reinterpret_cast<const Img*>(ws + kWsImgOffset);
+    const Img d = table[b];
+    if (d.H == 0) {
+        if (threadIdx.x == 0 && progress) progress[b] = -2;
+        return;
+    }
     CV::carve_image(d, 0, 1, sm, max_seams);
     __syncthreads();
     if (threadIdx.x == 0 && progress) {
@@ -724,6 +769,9 @@ __global__ __launch_bounds__(NT, 4) void carve_steps_kernel(char* const* __restr
         progress[b] = (ctl->status & (kStatusTimeout | kStatusPlacement)) ? -1 : (int)ctl->done;
     }
 }
+
+// Slot management: write (or clear) one descriptor of the slot table.
+__global__ void slot_write_kernel(Img* table, int slot, Img d) { table[slot] = d; }
 
 // Unpack the 2-bit direction map into bytes (row 0 has no parent: 1).
 __global__ void unpack_dirs_kernel(Img d, uint8_t* __restrict__ out) {
@@ -774,16 +822,21 @@ hipError_t launch_carve_batch(const Img* imgs, const int2* blk, const int2* team
     return hipGetLastError();
 }
 
-hipError_t launch_carve_steps(char* const* ws_list, int n, int v, int max_seams, int* progress, hipStream_t st) {
+hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, int* progress, hipStream_t st) {
     switch (v) {
-#define X(id, c, k, t)                                                                                       \
-    case id:                                                                                                 \
-        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, ws_list, n, max_seams, progress); \
+#define X(id, c, k, t)                                                                                        \
+    case id:                                                                                                  \
+        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, table, n, max_seams, progress); \
         break;
         SC_VARIANTS(X)
 #undef X
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st) {
+    hipLaunchKernelGGL(slot_write_kernel, dim3(1), dim3(1), 0, st, table, slot, d);
     return hipGetLastError();
 }
 
