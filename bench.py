@@ -47,18 +47,38 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def byte_model(H: int, W: int, seams: np.ndarray) -> int:
-    """Algorithmic HBM bytes of the carve loop of one image (C = 3), from its recorded seams.
+def byte_model(H: int, W: int, seams: np.ndarray, C: int = 3) -> int:
+    """Algorithmic HBM bytes of the carve loop of one image, from its recorded seams.
 
-    Per seam on an image of current width w: the DP reads the uint16 energy plane and writes a
-    2-bit direction per cell (2.25 B per pixel); removal reads and writes, right of the seam,
-    3 RGB bytes and 2 energy bytes per pixel (10 B per shifted pixel).
+    The method's loop per seam on an image of current width w: the DP reads the uint16 energy
+    plane and writes a 2-bit direction per cell (2.25 B per pixel); removal shifts every pixel
+    right of the seam one column left, reading and writing C image bytes and 2 energy bytes
+    (10 B per shifted RGB pixel).
     """
+    total = 0
+    for j in range(seams.shape[0]):
+        w = W - j
+        total += int(2.25 * H * w) + (2 * C + 4) * int((w - 1 - seams[j].astype(np.int64)).sum())
+    return total
+
+
+def moved_bytes(H: int, W: int, seams: np.ndarray, minside: bool, C: int = 3) -> int:
+    """Bytes the kernel itself moves for the same carve: as byte_model, but with min-side removal
+    only the shorter side of each row shifts, and rows that lost pixels on their left are moved
+    back to column 0 once at the end (2 C bytes per kept pixel)."""
+    if not minside:
+        return byte_model(H, W, seams, C)
     k = seams.shape[0]
     total = 0
+    left = np.zeros(H, dtype=np.int64)
     for j in range(k):
         w = W - j
-        total += int(2.25 * H * w) + 10 * int((w - 1 - seams[j].astype(np.int64)).sum())
+        s = seams[j].astype(np.int64)
+        side = s < w - 1 - s
+        left += side
+        total += int(2.25 * H * w) + (2 * C + 4) * int(np.where(side, s, w - 1 - s).sum())
+    if k:
+        total += 2 * C * (W - k) * int((left > 0).sum())
     return total
 
 
@@ -73,11 +93,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--team", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--no-minside", action="store_true",
+                    help="remove every seam pixel by shifting the right part (no min-side removal)")
     ap.add_argument("--n", type=int, default=256, help="images in the batch (256 = the configuration)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -91,6 +115,15 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        n = 1 << 30
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
+        return
     jobs = synth.batch_jobs(n=args.n)
     t0 = time.time()
     imgs_np = [j.image() for j in jobs]
@@ -102,7 +135,8 @@ def main():
     seams_total = sum(j.seams for j in jobs)
     torch.cuda.synchronize()
 
-    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant)
+    minside = not args.no_minside
+    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant, minside=minside)
     stream = torch.cuda.current_stream()
 
     def step(evs=None):
@@ -146,15 +180,18 @@ def main():
 
     # algorithmic bytes of one carve launch, from the recorded seams
     res = bc.results()
-    model_bytes = 0
+    model_bytes = moved = 0
     for j, (_, seams, _) in zip(jobs, res):
         if seams is not None:
-            model_bytes += byte_model(j.h, j.w, seams.cpu().numpy())
+            sn = seams.cpu().numpy()
+            model_bytes += byte_model(j.h, j.w, sn)
+            moved += moved_bytes(j.h, j.w, sn, minside)
     carve_s = float(np.mean(carve_ms)) / 1000.0
     achieved = model_bytes / carve_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                 "kernel": "carve_batch_kernel", "model_bytes_per_launch": model_bytes,
+                "kernel_moved_bytes_per_launch": moved,
                 "kernel_ms": round(float(np.mean(carve_ms)), 3)}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -178,7 +215,7 @@ def main():
         "config": {"workload": f"batched carve: {len(jobs)} RGB uint8 blob+noise images, H,W~U[240,2160], "
                                "10-40% of width removed (seed 3)",
                    "images": len(jobs), "seams": seams_total, "pixel_seams": pixel_seams,
-                   "team": bc.info.team, "variant": api.variants()[bc.info.variant]},
+                   "team": bc.info.team, "variant": api.variants()[bc.info.variant], "minside": minside},
         "roofline": roofline,
         "hbm_gbps_step": round(model_bytes / (ms_per_step / 1000.0) / 1e9, 1),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
@@ -216,7 +253,8 @@ def main():
         tp = time.perf_counter()
         for i in idx:
             ti = time.perf_counter()
-            api.carve(dsts[i], targets[i], src=srcs[i], record=False, team=args.team, variant=args.variant, ws=ws)
+            api.carve(dsts[i], targets[i], src=srcs[i], record=False, team=args.team, variant=args.variant, ws=ws,
+                      minside=minside)
             torch.cuda.synchronize()
             plat.append((time.perf_counter() - ti) * 1000.0)
         tp = time.perf_counter() - tp

@@ -105,9 +105,14 @@ sc_status sc_transpose_u8(const uint8_t* src, int H, int W, int C, int src_pitch
 /* Launch shape of the persistent carve kernel; NULL selects the built-in choice. */
 typedef struct {
     int team;    /* workgroups working together on one image (0 = default: 8 for sc_carve,
-                    at most 4 per image in a batch; teams run on one XCD) */
+                    at most 16 per image in a batch; teams run on one XCD) */
     int variant; /* kernel variant id (see sc_variant_count); -1 = default */
+    int flags;   /* SC_TUNE_* bits */
 } sc_tune;
+
+/* Remove every seam pixel by moving the pixels right of it (the paper's removal literally)
+ * instead of moving whichever side of the row is shorter.  Results are identical. */
+#define SC_TUNE_NO_MINSIDE 1
 
 /* Number of compiled kernel variants and a description of variant v (host memory, static). */
 int sc_variant_count(void);

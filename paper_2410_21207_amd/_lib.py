@@ -18,7 +18,10 @@ P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
 
 
 class sc_tune(ctypes.Structure):
-    _fields_ = [("team", ctypes.c_int), ("variant", ctypes.c_int)]
+    _fields_ = [("team", ctypes.c_int), ("variant", ctypes.c_int), ("flags", ctypes.c_int)]
+
+
+SC_TUNE_NO_MINSIDE = 1
 
 
 class sc_job(ctypes.Structure):

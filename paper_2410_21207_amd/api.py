@@ -92,14 +92,16 @@ def transpose(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -
     return out
 
 
-def _tune(team=None, variant=None):
-    if team is None and variant is None:
+def _tune(team=None, variant=None, minside=True):
+    if team is None and variant is None and minside:
         return None
-    return ctypes.byref(_lib.sc_tune(team or 0, -1 if variant is None else variant))
+    return ctypes.byref(_lib.sc_tune(team or 0, -1 if variant is None else variant,
+                                     0 if minside else _lib.SC_TUNE_NO_MINSIDE))
 
 
 def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,
-          team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None):
+          team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None,
+          minside: bool = True):
     """Carve `img` to target_w columns (in place; from `src` when given).
 
     Returns (img[:, :target_w], seams int32 [k, H] or None, costs int64 [k] or None).
@@ -119,7 +121,7 @@ def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, rec
         seams = torch.empty((k, H), dtype=torch.int32, device=img.device)
         costs = torch.empty(k, dtype=torch.int64, device=img.device)
     _lib.call("sc_carve", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
-              _tune(team, variant), _ptr(ws), ws.numel(), _stream(stream))
+              _tune(team, variant, minside), _ptr(ws), ws.numel(), _stream(stream))
     return img[:, : int(target_w)], seams, costs
 
 
@@ -193,7 +195,7 @@ class BatchCarver:
     """
 
     def __init__(self, imgs, targets, srcs=None, record: bool = True, team: int | None = None,
-                 variant: int | None = None):
+                 variant: int | None = None, minside: bool = True):
         self.jobs = []
         for i, (img, tw) in enumerate(zip(imgs, targets)):
             H, W, C, pitch = _image(img)
@@ -211,7 +213,8 @@ class BatchCarver:
             self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
                                          pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
                                          None if j.costs is None else j.costs.data_ptr())
-        self._tune = _lib.sc_tune(team or 0, -1 if variant is None else variant)
+        self._tune = _lib.sc_tune(team or 0, -1 if variant is None else variant,
+                                  0 if minside else _lib.SC_TUNE_NO_MINSIDE)
         need = _lib.load().sc_batch_workspace_bytes(self._cjobs, n)
         if need == 0:
             raise ValueError("bad batch")

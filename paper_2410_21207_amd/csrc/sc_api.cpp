@@ -46,7 +46,7 @@ static_assert(sizeof(sc::Ctl) == 64, "ctl size");
 
 constexpr int kMaxCostBound = 8388000;  // H*510*C: the column cost must fit 23 bits
 constexpr int kDefaultTeamSingle = 8;   // workgroups carving one image (sc_carve)
-constexpr int kDefaultTeamBatch = 4;    // largest team for one image of a batch
+constexpr int kDefaultTeamBatch = 16;   // largest team for one image of a batch
 
 sc_status check_image(int H, int W, int C, int pitch) {
     if (H < 1 || W < 1) return fail(SC_EINVAL, "H=%d W=%d must be >= 1", H, W);
@@ -81,6 +81,8 @@ sc::Img make_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long lon
     d.anc = reinterpret_cast<int8_t*>(base + L.anc);
     d.xq = reinterpret_cast<uint32_t*>(base + L.xq);
     d.seam = reinterpret_cast<int32_t*>(base + L.seam);
+    d.ro = reinterpret_cast<int32_t*>(base + L.ro);
+    d.minside = 1;
     d.amin = &ctl->amin;
     d.bar = &ctl->bar;
     d.status = &ctl->status;
@@ -120,6 +122,8 @@ Layout layout_for(int H, int W, int kr_min) {
     L.xq = off;
     off = align_up(off + (size_t)2 * L.xw * 4, kAlign);
     L.seam = off;
+    off = align_up(off + (size_t)H * 4, kAlign);
+    L.ro = off;
     off = align_up(off + (size_t)H * 4, kAlign);
     L.total = off;
     return L;
@@ -216,6 +220,7 @@ sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pi
     sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
     sc::Img d = make_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out, base + ctl_region(1), ctl,
                          sc::variant(v).kr, G, 0);
+    if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) d.minside = 0;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = sc::launch_prepare_single(d, st);
     if (e == hipSuccess && target_w < W) e = sc::launch_carve_single(d, v, G, st);
@@ -339,6 +344,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
         sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead)) + i;
         imgs[i] = make_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
                            base + off_data, ctl, sc::variant(v).kr, gsz[i], 0);
+        if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) imgs[i].minside = 0;
         off_data += sc::layout_for(j.H, j.W, 32).total;
         max_rows = std::max(max_rows, j.H);
     }

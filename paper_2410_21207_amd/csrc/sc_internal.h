@@ -21,13 +21,15 @@ struct Img {
     int8_t* anc;   // per DP phase, the ancestor offset of every column at the phase's last row
     uint32_t* xq;  // 2 rows of `xw` uint32: DP keys exchanged between waves at phase ends
     int32_t* seam; // current seam, H
+    int32_t* ro;   // per row: physical column of the row's first pixel (min-side removal), H
     unsigned long long* amin;  // packed (cost << 32 | column) argmin of the current seam
     unsigned* bar;             // team barrier counter
     unsigned* status;          // error bits
     int ep, db, xw, P;         // pitches and the number of DP phases
     int G;                     // team size (workgroups) carving this image
     int mode;                  // 0 = carve, 1 = one seam only, no removal (sc_dp_seam)
-    int pad0, pad1;
+    int minside;               // 1 = remove a seam pixel by moving the shorter side of its row
+    int pad1;
 };
 
 // Control words of one image (zeroed by the energy pass of every launch).
@@ -45,7 +47,7 @@ constexpr unsigned kStatusPlacement = 2u;  // a team's workgroups were not on on
 
 // Placement of one image's scratch inside a workspace.
 struct Layout {
-    size_t ctl, e, dirs, anc, xq, seam, total;
+    size_t ctl, e, dirs, anc, xq, seam, ro, total;
     int ep, db, xw, P;
 };
 

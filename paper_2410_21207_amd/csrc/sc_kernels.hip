@@ -107,6 +107,21 @@ __device__ __forceinline__ uint32_t energy_at(const uint8_t* img, long long pitc
     return s;
 }
 
+// e1 energy at logical column x of a row whose pixel 0 is at `r`, with the rows above and below
+// given the same way (min-side removal keeps every row at its own offset).
+template <bool COH>
+__device__ __forceinline__ uint32_t energy_rows(const uint8_t* r, const uint8_t* ru, const uint8_t* rd, int w, int C,
+                                                int x) {
+    const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < w ? x + 1 : w - 1;
+    uint32_t s = 0;
+    for (int c = 0; c < C; ++c) {
+        const int dx = (int)ld<COH>(r + xr * C + c) - (int)ld<COH>(r + xl * C + c);
+        const int dy = (int)ld<COH>(rd + x * C + c) - (int)ld<COH>(ru + x * C + c);
+        s += (uint32_t)(dx < 0 ? -dx : dx) + (uint32_t)(dy < 0 ? -dy : dy);
+    }
+    return s;
+}
+
 // Standalone energy map (int32, dense).
 __global__ void energy_i32_kernel(const uint8_t* __restrict__ img, int H, int W, int C, long long pitch,
                                   int32_t* __restrict__ out) {
@@ -140,6 +155,7 @@ __device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
     const uint8_t* srcimg = d.src ? d.src : d.img;
     if (row_begin == 0 && threadIdx.x == 0) reset_ctl(d);
     for (int y = row_begin; y < d.H; y += row_step) {
+        if (threadIdx.x == 0) *gp(d.ro + y) = 0;
         uint16_t* er = d.e + (long long)y * d.ep;
         for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
             *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
@@ -172,6 +188,7 @@ __global__ void prepare_from_i32_kernel(Img d, const int32_t* __restrict__ e) {
         reset_ctl(d);
     }
     const int y = blockIdx.y;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *gp(d.ro + y) = 0;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < d.W; x += gridDim.x * blockDim.x)
         *gp(d.e + (long long)y * d.ep + x) = (uint16_t)*gp(e + (long long)y * d.W + x);
 }
@@ -267,6 +284,115 @@ __device__ __forceinline__ void shift_segments_wave(uint8_t* a_lo_p, uint8_t* a_
         seg_load<U, COH>(B, fb, lane, DB);
         seg_store<U>(A, fb, lane, DA);
         seg_store<U>(B, fb, lane, DB);
+    }
+}
+
+// In-place RIGHT shift of up to two row segments by one pixel, one wave: the bytes of [lo, hi)
+// move to [lo + sh, hi + sh) (min-side removal of a seam pixel from the left part of a row).
+// Slots are processed from the highest address down; a slot's output needs its own 16 bytes and
+// the dword just below it, which belongs to the next lower slot -- loaded in the same pass or a
+// later one, and a pass issues all its loads before its stores, so the update is hazard free.
+template <int U>
+__device__ __forceinline__ void seg_right(uint8_t* lo_p, uint8_t* hi_p, int sh, int fb, int lane, bool load,
+                                          uint32_t (&D)[U][5]) {
+    // destination [lo + sh, hi + sh) in 16-byte slots counted DOWN from the last one
+    const uintptr_t dlo = (uintptr_t)lo_p + sh, dhi = (uintptr_t)hi_p + sh;
+    if (dlo >= dhi) return;
+    const int qoff = (int)(dlo & 15);
+    uint8_t* const base = lo_p + sh - qoff;          // slot-aligned base of the destination
+    const int end = qoff + (int)(dhi - dlo);         // destination as [qoff, end) from base
+    const int n = ((end - 1) >> 4) + 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int f = fb + u * 64 + lane;
+        if (f >= n) continue;
+        const int so = (n - 1 - f) << 4;  // slot offset from base, highest slot first
+        uint8_t* sp = base + so;
+        if (load) {
+            const uint64_t* q = reinterpret_cast<const uint64_t*>(sp);
+            const uint64_t v0 = *gp(q), v1 = *gp(q + 1);
+            D[u][1] = (uint32_t)v0; D[u][2] = (uint32_t)(v0 >> 32);
+            D[u][3] = (uint32_t)v1; D[u][4] = (uint32_t)(v1 >> 32);
+            // the dword below the slot is needed when the slot starts above the source start
+            D[u][0] = (uintptr_t)sp > (uintptr_t)lo_p ? *gp(reinterpret_cast<const uint32_t*>(sp - 4)) : 0u;
+        } else {
+            uint32_t o[4];
+            if (sh == 4) {
+                o[0] = D[u][0]; o[1] = D[u][1]; o[2] = D[u][2]; o[3] = D[u][3];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(D[u][i + 1], D[u][i], (uint32_t)(4 - sh));
+            }
+            if (so >= qoff && so + 16 <= end) {
+                *gp(reinterpret_cast<u32x4*>(sp)) = u32x4{o[0], o[1], o[2], o[3]};
+            } else {
+                const int k0 = so > qoff ? 0 : qoff - so;
+                const int k1 = so + 16 < end ? 16 : end - so;
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if (k >= k0 && k < k1) *gp(sp + k) = (uint8_t)(o[k >> 2] >> ((k & 3) * 8));
+            }
+        }
+    }
+}
+
+template <int U>
+__device__ __forceinline__ void shift_right_segments_wave(uint8_t* a_lo, uint8_t* a_hi, int sh_a, uint8_t* b_lo,
+                                                          uint8_t* b_hi, int sh_b, int lane) {
+    auto slots = [](uint8_t* lo, uint8_t* hi, int sh) {
+        const uintptr_t dlo = (uintptr_t)lo + sh, dhi = (uintptr_t)hi + sh;
+        return dlo < dhi ? (int)((((dlo & 15) + (dhi - dlo)) - 1) >> 4) + 1 : 0;
+    };
+    const int n = max(slots(a_lo, a_hi, sh_a), slots(b_lo, b_hi, sh_b));
+#pragma unroll 1
+    for (int fb = 0; fb < n; fb += 64 * U) {
+        uint32_t DA[U][5], DB[U][5];
+        seg_right<U>(a_lo, a_hi, sh_a, fb, lane, true, DA);
+        seg_right<U>(b_lo, b_hi, sh_b, fb, lane, true, DB);
+        seg_right<U>(a_lo, a_hi, sh_a, fb, lane, false, DA);
+        seg_right<U>(b_lo, b_hi, sh_b, fb, lane, false, DB);
+    }
+}
+
+// dst bytes [dst, dst + n) take the values of [dst + sh, dst + sh + n), sh > 0, one wave (moves a
+// row back to column 0 after min-side removal).  Dword-granular: a pass loads its source dwords
+// (ascending, all above everything stored so far) before its stores.
+__device__ __forceinline__ void move_left_wave(uint8_t* dst, int n, int sh, int lane) {
+    if (n <= 0 || sh <= 0) return;
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + n;
+    const int off = (int)(d0 & 3);
+    uint8_t* const base = dst - off;                 // dword-aligned; output dword j covers base + 4j
+    const int nd = ((off + n - 1) >> 2) + 1;
+    const uintptr_t s_end = d1 + sh;                 // source bytes end here
+    constexpr int U = 4;
+#pragma unroll 1
+    for (int jb = 0; jb < nd; jb += 64 * U) {
+        uint32_t lo[U], hi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = jb + u * 64 + lane;
+            lo[u] = hi[u] = 0;
+            if (j < nd) {
+                const uintptr_t sa = (uintptr_t)base + 4 * j + sh;  // first source byte of dword j
+                const uint32_t* sp = reinterpret_cast<const uint32_t*>(base + ((4 * j + sh) & ~3));
+                lo[u] = *gp(sp);
+                if ((sa & 3) && ((sa & ~(uintptr_t)3) + 4) < s_end) hi[u] = *gp(sp + 1);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = jb + u * 64 + lane;
+            if (j >= nd) continue;
+            const uint32_t v = __builtin_amdgcn_alignbyte(hi[u], lo[u], (uint32_t)((4 * j + sh) & 3));
+            uint8_t* dp = base + 4 * j;
+            if ((uintptr_t)dp >= d0 && (uintptr_t)dp + 4 <= d1) {
+                *gp(reinterpret_cast<uint32_t*>(dp)) = v;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((uintptr_t)dp + k >= d0 && (uintptr_t)dp + k < d1) *gp(dp + k) = (uint8_t)(v >> (8 * k));
+            }
+        }
     }
 }
 
@@ -369,16 +495,17 @@ struct Carver {
         uint64_t v[CPL / 4];  // CPL uint16 energies
     };
 
-    // Energies of row r (wave-uniform, a valid row) at the lane's byte offset `off` (a valid
-    // column): a buffer load with the row offset in a scalar register.  COH sets the sc1 bit.
+    // Energies at the lane's byte offset `off` (a valid column) of the row starting `soff` bytes
+    // into the plane (wave-uniform: row base plus the row's start offset): a buffer load with the
+    // row part in a scalar register.  COH sets the sc1 bit.
     template <bool COH>
-    static __device__ __forceinline__ EV load_ev(__amdgpu_buffer_rsrc_t re, uint32_t row_bytes, int r, uint32_t off) {
+    static __device__ __forceinline__ EV load_ev(__amdgpu_buffer_rsrc_t re, uint32_t soff, uint32_t off) {
         EV e;
         if constexpr (CPL == 4) {
-            const v2u v = __builtin_amdgcn_raw_buffer_load_b64(re, (int)off, (int)((uint32_t)r * row_bytes), COH ? 16 : 0);
+            const v2u v = __builtin_amdgcn_raw_buffer_load_b64(re, (int)off, (int)soff, COH ? 16 : 0);
             e.v[0] = ((uint64_t)v[1] << 32) | v[0];
         } else {
-            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(re, (int)off, (int)((uint32_t)r * row_bytes), COH ? 16 : 0);
+            const v4u v = __builtin_amdgcn_raw_buffer_load_b128(re, (int)off, (int)soff, COH ? 16 : 0);
             e.v[0] = ((uint64_t)v[1] << 32) | v[0];
             e.v[1] = ((uint64_t)v[3] << 32) | v[2];
         }
@@ -449,9 +576,22 @@ struct Carver {
         const uint32_t erb = (uint32_t)d.ep * 2u;                       // bytes per energy row
         const __amdgpu_buffer_rsrc_t re = make_rsrc(d.e, (uint32_t)d.H * erb);
         const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)d.H * (uint32_t)d.db);
+        // start offsets of this item's rows and of the next item's rows: lane l holds row r0 + l
+        const int last = d.H - 1;
+        const int rov = lane < KR ? ld<TEAM>(d.ro + min(r0 + lane, last)) : 0;
+        const int rovn = lane < KR ? ld<TEAM>(d.ro + min(nx.r0 + lane, last)) : 0;
+        // byte offset of row r0 + i of this item (i < KR), wave-uniform
+        auto soff = [&](int i) {
+            const int r = min(r0 + i, last);
+            return (uint32_t)r * erb + 2u * (uint32_t)__builtin_amdgcn_readlane(rov, r - r0);
+        };
+        auto soffn = [&](int i) {
+            const int r = min(nx.r0 + i, last);
+            return (uint32_t)r * erb + 2u * (uint32_t)__builtin_amdgcn_readlane(rovn, r - nx.r0);
+        };
         if (!preloaded) {
 #pragma unroll
-            for (int i = 0; i < PF; ++i) ring[i] = load_ev<TEAM>(re, erb, min(r0 + i, d.H - 1), eoff);
+            for (int i = 0; i < PF; ++i) ring[i] = load_ev<TEAM>(re, soff(i), eoff);
         }
         // previous row's keys.  Phase 0 starts from a row of zeros: one ordinary DP step then gives
         // M(0,j) = e(0,j) (its directions and offsets are never read).
@@ -502,17 +642,18 @@ struct Carver {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
                 const EV ev = ring[i];
-                ring[i] = load_ev<TEAM>(re, erb, rb + i + PF, eoff);
+                ring[i] = load_ev<TEAM>(re, soff(rb - r0 + i + PF), eoff);
                 step(rb + i, ev);
             }
         }
-        // the last full block prefetches the next item's first rows (or reloads its own, unused)
+        // the last full block prefetches the next item's first rows, or else this item's partial
+        // tail (rows past the item's end are clamped to its last row and never stepped)
         if (rb + PF <= r1) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
                 const EV ev = ring[i];
-                const int rn = cross ? min(nx.r0 + i, d.H - 1) : rb + i;
-                ring[i] = load_ev<TEAM>(re, erb, rn, cross ? nx.off : eoff);
+                ring[i] = load_ev<TEAM>(re, cross ? soffn(i) : soff(min(rb - r0 + PF + i, r1 - 1 - r0)),
+                                        cross ? nx.off : eoff);
                 step(rb + i, ev);
             }
             rb += PF;
@@ -646,14 +787,23 @@ struct Carver {
                     // ---- removal (a6) of this phase's rows: image bytes and energy plane.  A row is
                     // only ever written by the wave owning its phase (this shift and the band update
                     // below) or by the earlier energy pass, so plain loads see its current bytes even
-                    // in a team.
+                    // in a team.  With min-side removal the shorter side of the row moves: pixels
+                    // right of the seam one column left, or pixels left of it one column right with
+                    // the row's start offset advanced by one.
+                    const int rof = lane < n ? *gp(d.ro + r0 + lane) : 0;
 #pragma unroll 1
                     for (int i = 0; i < n; ++i) {
                         const int si = __builtin_amdgcn_readlane(mys, i);  // wave-uniform: scalar addresses
-                        uint8_t* row = d.img + (long long)(r0 + i) * d.pitch;
-                        uint8_t* er = reinterpret_cast<uint8_t*>(d.e + (size_t)(r0 + i) * d.ep);
-                        shift_segments_wave<4, false>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C, d.C,
-                                                     er + 2 * si, er + 2 * (w - 1), 2, lane);
+                        const int o = __builtin_amdgcn_readlane(rof, i);
+                        uint8_t* row = d.img + (long long)(r0 + i) * d.pitch + (long long)o * d.C;
+                        uint8_t* er = reinterpret_cast<uint8_t*>(d.e + (size_t)(r0 + i) * d.ep + o);
+                        if (d.minside && si < w - 1 - si) {
+                            shift_right_segments_wave<4>(row, row + (long long)si * d.C, d.C, er, er + 2 * si, 2, lane);
+                            if (lane == 0) *gp(d.ro + r0 + i) = o + 1;
+                        } else {
+                            shift_segments_wave<4, false>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C,
+                                                         d.C, er + 2 * si, er + 2 * (w - 1), 2, lane);
+                        }
                     }
                 }
             }
@@ -669,9 +819,14 @@ struct Carver {
                 const int r = r0 + lane;
                 if (r < r1) {
                     const int s = min(max(ld<TEAM>(d.seam + r), 0), w - 1);
-                    uint16_t* er = d.e + (size_t)r * d.ep;
-                    if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)energy_at<TEAM>(d.img, d.pitch, H, w2, d.C, r, s - 1);
-                    if (s < w2) *gp(er + s) = (uint16_t)energy_at<TEAM>(d.img, d.pitch, H, w2, d.C, r, s);
+                    const int ru = r > 0 ? r - 1 : 0, rd = r + 1 < H ? r + 1 : H - 1;
+                    const int o = ld<TEAM>(d.ro + r);
+                    const uint8_t* pr = d.img + (long long)r * d.pitch + (long long)o * d.C;
+                    const uint8_t* pu = d.img + (long long)ru * d.pitch + (long long)ld<TEAM>(d.ro + ru) * d.C;
+                    const uint8_t* pd = d.img + (long long)rd * d.pitch + (long long)ld<TEAM>(d.ro + rd) * d.C;
+                    uint16_t* er = d.e + (size_t)r * d.ep + o;
+                    if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s - 1);
+                    if (s < w2) *gp(er + s) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s);
                 }
             }
             if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
@@ -681,6 +836,20 @@ struct Carver {
                 ctl->t_stage[1] += tm2 - tm1;
                 ctl->t_stage[2] += tm3 - tm2;
             }
+        }
+        // ---- after the last seam, move rows carved from the left back to column 0
+        if (!d.mode && d.minside && k_end == d.W - d.target_w && k_end > k_begin) {
+            const int tw_px = d.target_w;
+            for (int p = tw; p < P; p += TW) {
+                const int r0 = p * KR, r1 = min(H, r0 + KR), n = r1 - r0;
+                const int rof = lane < n ? *gp(d.ro + r0 + lane) : 0;
+#pragma unroll 1
+                for (int i = 0; i < n; ++i) {
+                    const int o = __builtin_amdgcn_readlane(rof, i);
+                    if (o > 0) move_left_wave(d.img + (long long)(r0 + i) * d.pitch, tw_px * d.C, o * d.C, lane);
+                }
+            }
+            team_sync<TEAM>(d, epoch, G, &sm.flag);
         }
     }
 
@@ -791,13 +960,16 @@ static const Variant kVariants[] = {
     {4, 32, 1024, "cpl4_k32_t1024"},
     {8, 32, 512, "cpl8_k32_t512"},
     {8, 32, 1024, "cpl8_k32_t1024"},
+    {4, 48, 512, "cpl4_k48_t512"},
+    {4, 48, 256, "cpl4_k48_t256"},
 };
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v]; }
 int default_variant() { return 1; }
 int team_variant() { return 1; }
 
-#define SC_VARIANTS(X) X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024)
+#define SC_VARIANTS(X) \
+    X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) X(6, 4, 48, 256)
 
 hipError_t launch_carve_single(const Img& d, int v, int G, hipStream_t st) {
     switch (v) {

@@ -219,6 +219,8 @@ class GPUExecutor:
         src = t.payload
         if not isinstance(src, torch.Tensor) or not src.is_cuda:
             src = torch.as_tensor(src).to(self.device, non_blocking=True)
+        if tuple(src.shape) != (t.h, t.w, t.c):
+            raise ValueError(f"payload shape {tuple(src.shape)} != request ({t.h}, {t.w}, {t.c})")
         img = torch.empty_like(src)
         ws = api.workspace(self.lib.sc_workspace_bytes(t.h, t.w, t.c), self.device)
         k = t.seams

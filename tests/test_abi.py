@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(_lib.sc_job) == 8 + 8 + 5 * 4 + 4 + 8 + 8  # padding after target_w
-    assert ctypes.sizeof(_lib.sc_tune) == 8
+    assert ctypes.sizeof(_lib.sc_tune) == 12
     assert ctypes.sizeof(_lib.sc_batch_info) == 6 * 4 + 4 * 8
 
 

@@ -120,6 +120,23 @@ def test_carve_tie_heavy_and_edges(H, W, C, tw, alpha):
     _carve_and_compare(rng_img(H * W + alpha, H, W, C, alpha), tw)
 
 
+@pytest.mark.parametrize("minside", [True, False])
+@pytest.mark.parametrize("H,W,C,tw,team", [(61, 333, 3, 250, 1), (45, 260, 1, 100, 2), (70, 419, 4, 300, 4),
+                                           (33, 129, 2, 1, 1), (130, 500, 3, 440, 8)])
+def test_carve_removal_side(H, W, C, tw, team, minside):
+    """Min-side removal (shift the shorter side of each row, rows re-based at the end) and
+    right-side removal give the oracle's result; row padding beyond W is never written."""
+    log("carve removal side", H, W, C, tw, team, minside)
+    img = synth.blob_image(H, W, C, seed=H + W) if C == 3 else rng_img(H * W, H, W, C, 8)
+    t = padded(img, 5)
+    out, seams, costs = api.carve(t, tw, team=team, minside=minside)
+    o_out, o_seams, o_costs = oracle.carve(img, tw)
+    assert np.array_equal(host(seams), o_seams) and np.array_equal(host(costs), o_costs)
+    assert np.array_equal(host(out), o_out)
+    full = host(t.as_strided((H, W + 5, C), t.stride()))
+    assert (full[:, W:] == 0xAB).all(), "padding written"
+
+
 def test_carve_wider_than_lds_row():
     """W > 4096: the phase exchange row no longer fits LDS, so even one workgroup uses the team path."""
     img = synth.blob_image(40, 4500, 3, seed=31)
@@ -212,13 +229,14 @@ def _batch_jobs(seed, n, lo, hi):
     return jobs
 
 
+@pytest.mark.parametrize("minside", [True, False])
 @pytest.mark.parametrize("team", [1, 2, 4])
-def test_batch_parity(team):
+def test_batch_parity(team, minside):
     jobs = _batch_jobs(7, 14, 20, 420)
     srcs = [dev(img) for img, _ in jobs]
     imgs = [torch.empty_like(s) for s in srcs]
-    log("batch team", team)
-    bc = api.BatchCarver(imgs, [tw for _, tw in jobs], srcs=srcs, team=team)
+    log("batch team", team, "minside", minside)
+    bc = api.BatchCarver(imgs, [tw for _, tw in jobs], srcs=srcs, team=team, minside=minside)
     bc.launch()
     res = bc.results()
     for (img, tw), (out, seams, costs) in zip(jobs, res):

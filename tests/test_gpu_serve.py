@@ -46,7 +46,7 @@ def test_served_in_mix_equals_alone(seams_per_step):
 
 
 def test_open_loop_serving_short():
-    reqs = synth.serving_requests(rate=200.0, duration=0.5, seed=9, side=(64, 512))
+    reqs = synth.serving_requests(rate=200.0, duration=0.5, seed=9, side=(64, 512), canvas_side=512)
     canvases = [dev(synth.blob_image(512, 512, 3, seed=2000 + i)) for i in range(16)]
     srv = Server(GPUExecutor(64), budget_bytes=4 << 30, max_slots=64, seams_per_step=16)
     st = srv.run(reqs, lambda r: canvases[r.canvas][r.y0:r.y0 + r.h, r.x0:r.x0 + r.w].contiguous())
