@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--team", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--no-prio", action="store_true",
+                    help="run every image at the same wave priority")
     ap.add_argument("--no-minside", action="store_true",
                     help="remove every seam pixel by shifting the right part (no min-side removal)")
     ap.add_argument("--n", type=int, default=256, help="images in the batch (256 = the configuration)")
@@ -136,7 +138,8 @@ def main():
     torch.cuda.synchronize()
 
     minside = not args.no_minside
-    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant, minside=minside)
+    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant, minside=minside,
+                         prio=not args.no_prio)
     stream = torch.cuda.current_stream()
 
     def step(evs=None):
@@ -215,7 +218,8 @@ def main():
         "config": {"workload": f"batched carve: {len(jobs)} RGB uint8 blob+noise images, H,W~U[240,2160], "
                                "10-40% of width removed (seed 3)",
                    "images": len(jobs), "seams": seams_total, "pixel_seams": pixel_seams,
-                   "team": bc.info.team, "variant": api.variants()[bc.info.variant], "minside": minside},
+                   "team": bc.info.team, "variant": api.variants()[bc.info.variant], "minside": minside,
+                   "prio": not args.no_prio},
         "roofline": roofline,
         "hbm_gbps_step": round(model_bytes / (ms_per_step / 1000.0) / 1e9, 1),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),

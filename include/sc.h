@@ -113,6 +113,9 @@ typedef struct {
 /* Remove every seam pixel by moving the pixels right of it (the paper's removal literally)
  * instead of moving whichever side of the row is shorter.  Results are identical. */
 #define SC_TUNE_NO_MINSIDE 1
+/* Batches: run every image at the same wave priority (by default the images with the longest
+ * seams-by-rows chains run at a raised priority on their SIMDs).  Results are identical. */
+#define SC_TUNE_NO_PRIO 2
 
 /* Number of compiled kernel variants and a description of variant v (host memory, static). */
 int sc_variant_count(void);

@@ -195,7 +195,7 @@ class BatchCarver:
     """
 
     def __init__(self, imgs, targets, srcs=None, record: bool = True, team: int | None = None,
-                 variant: int | None = None, minside: bool = True):
+                 variant: int | None = None, minside: bool = True, prio: bool = True):
         self.jobs = []
         for i, (img, tw) in enumerate(zip(imgs, targets)):
             H, W, C, pitch = _image(img)
@@ -214,7 +214,7 @@ class BatchCarver:
                                          pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
                                          None if j.costs is None else j.costs.data_ptr())
         self._tune = _lib.sc_tune(team or 0, -1 if variant is None else variant,
-                                  0 if minside else _lib.SC_TUNE_NO_MINSIDE)
+                                  (0 if minside else _lib.SC_TUNE_NO_MINSIDE) | (0 if prio else _lib.SC_TUNE_NO_PRIO))
         need = _lib.load().sc_batch_workspace_bytes(self._cjobs, n)
         if need == 0:
             raise ValueError("bad batch")

@@ -288,6 +288,19 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     std::vector<int> gsz(n, 1);
     if (G > 1)
         for (int i = 0; i < n; ++i) gsz[i] = (int)std::min<double>(G, std::max(1.0, std::ceil(work[i] / per_slot)));
+    // Wave priorities: an image's latency grows with its row chain, seams x rows; images whose
+    // chain is within 2x, 4x, 8x of the longest get priority 3, 2, 1 on their SIMDs.
+    std::vector<int> prio(n, 0);
+    {
+        std::vector<double> chain(n);
+        double cmax = 1;
+        for (int i = 0; i < n; ++i) {
+            chain[i] = (double)(jobs[i].W - jobs[i].target_w) * (jobs[i].H + 64);
+            cmax = std::max(cmax, chain[i]);
+        }
+        for (int i = 0; i < n; ++i)
+            prio[i] = chain[i] * 2 >= cmax ? 3 : chain[i] * 4 >= cmax ? 2 : chain[i] * 8 >= cmax ? 1 : 0;
+    }
     std::vector<int2> blk, teams;
     std::vector<int> team_imgs;
     int slots[8] = {0};
@@ -345,6 +358,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
         imgs[i] = make_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
                            base + off_data, ctl, sc::variant(v).kr, gsz[i], 0);
         if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) imgs[i].minside = 0;
+        if (!(tune && (tune->flags & SC_TUNE_NO_PRIO))) imgs[i].prio = prio[i];
         off_data += sc::layout_for(j.H, j.W, 32).total;
         max_rows = std::max(max_rows, j.H);
     }

@@ -396,6 +396,18 @@ __device__ __forceinline__ void move_left_wave(uint8_t* dst, int n, int sh, int 
     }
 }
 
+// Issue priority of the calling wave against the other waves on its SIMD (0 lowest .. 3).  The
+// batch planner raises it for the images on the batch's critical path, so their row chains are
+// not slowed by the short images sharing their compute units.
+__device__ __forceinline__ void set_prio(int p) {
+    switch (p) {
+        case 3: __builtin_amdgcn_s_setprio(3); break;
+        case 2: __builtin_amdgcn_s_setprio(2); break;
+        case 1: __builtin_amdgcn_s_setprio(1); break;
+        default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
 // Standalone seam removal: one wave per row.
 __global__ void remove_seam_kernel(uint8_t* __restrict__ img, int H, int W, int C, long long pitch,
                                    const int32_t* __restrict__ seam) {
@@ -704,7 +716,11 @@ struct Carver {
     static __device__ __forceinline__ void carve_seams(const Img& d, int rank, int G, Smem& sm, int k_begin, int k_end,
                                        unsigned& epoch) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int TW = G * NW, tw = rank * NW + wv;
+        // waves are numbered across the team first, so a phase's strips land on different compute
+        // units (one DP wave per SIMD) before any workgroup takes a second one
+        const int TW = G * NW, tw = wv * G + rank;
+        const int rpw = (d.H + TW - 1) / TW;
+        const int ra = min(d.H, tw * rpw), rb = min(d.H, ra + rpw);  // rows this wave owns
         const int H = d.H, P = d.P;
         Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
         const bool timer = rank == 0 && threadIdx.x == 0;  // one clock reader per image
@@ -751,15 +767,19 @@ struct Carver {
                     __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
-            for (int p = tw; p < P; p += TW) {
+            // Each wave owns an equal range of rows [ra, rb) for the walk's output, the removal and
+            // the band update.  It walks every phase its range touches (bottom phase first: phase
+            // ends become known from the bottom up) and keeps the rows of its range.
+            for (int p = (rb - 1) / KR; ra < rb && p >= ra / KR; --p) {
                 const int r0 = p * KR, r1 = min(H, r0 + KR), n = r1 - r0;
+                const int ia = max(ra, r0) - r0, ib = min(rb, r1) - r0;  // this wave's rows of the phase
                 while (__hip_atomic_load(&sm.chain, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > p)
                     __builtin_amdgcn_s_sleep(1);
                 const int je = sm.jend[p];
                 const int dlo = (max(0, je - KR) >> 2) >> 2;
                 const int ndw = d.db >> 2;
                 uint32_t* win = sm.win[wv];
-                if (lane < n) {
+                if (lane >= ia && lane < n) {
                     const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs + (size_t)(r0 + lane) * d.db);
 #pragma unroll
                     for (int q = 0; q < WD; ++q) win[lane * WD + q] = (dlo + q < ndw) ? ld<TEAM>(src + dlo + q) : 0u;
@@ -768,7 +788,7 @@ struct Carver {
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 int s = je, mys = 0;
-                for (int i = n - 1; i >= 0; --i) {
+                for (int i = n - 1; i >= ia; --i) {
                     if (lane == i) mys = s;
                     if (i > 0) {
                         const int b = s >> 2;
@@ -778,21 +798,21 @@ struct Carver {
                         s = min(max(s, 0), w - 1);
                     }
                 }
-                if (lane < n) {
+                if (lane >= ia && lane < ib) {
                     *gp(d.seam + r0 + lane) = mys;
                     if (d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (!d.mode) {
-                    // ---- removal (a6) of this phase's rows: image bytes and energy plane.  A row is
-                    // only ever written by the wave owning its phase (this shift and the band update
-                    // below) or by the earlier energy pass, so plain loads see its current bytes even
-                    // in a team.  With min-side removal the shorter side of the row moves: pixels
-                    // right of the seam one column left, or pixels left of it one column right with
-                    // the row's start offset advanced by one.
-                    const int rof = lane < n ? *gp(d.ro + r0 + lane) : 0;
+                    // ---- removal (a6) of this wave's rows: image bytes and energy plane.  A row is
+                    // only ever written by the wave owning it (this shift, the band update below and
+                    // the final compaction) or by the earlier energy pass, so plain loads see its
+                    // current bytes even in a team.  With min-side removal the shorter side of the
+                    // row moves: pixels right of the seam one column left, or pixels left of it one
+                    // column right with the row's start offset advanced by one.
+                    const int rof = lane >= ia && lane < ib ? *gp(d.ro + r0 + lane) : 0;
 #pragma unroll 1
-                    for (int i = 0; i < n; ++i) {
+                    for (int i = ia; i < ib; ++i) {
                         const int si = __builtin_amdgcn_readlane(mys, i);  // wave-uniform: scalar addresses
                         const int o = __builtin_amdgcn_readlane(rof, i);
                         uint8_t* row = d.img + (long long)(r0 + i) * d.pitch + (long long)o * d.C;
@@ -814,10 +834,9 @@ struct Carver {
                 __hip_atomic_store(d.amin, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // ---- band energy (a2): only the new columns s-1 and s of each row changed
             const int w2 = w - 1;
-            for (int p = tw; p < P; p += TW) {
-                const int r0 = p * KR, r1 = min(H, r0 + KR);
-                const int r = r0 + lane;
-                if (r < r1) {
+            for (int rc = ra; rc < rb; rc += 64) {
+                const int r = rc + lane;
+                if (r < rb) {
                     const int s = min(max(ld<TEAM>(d.seam + r), 0), w - 1);
                     const int ru = r > 0 ? r - 1 : 0, rd = r + 1 < H ? r + 1 : H - 1;
                     const int o = ld<TEAM>(d.ro + r);
@@ -840,13 +859,13 @@ struct Carver {
         // ---- after the last seam, move rows carved from the left back to column 0
         if (!d.mode && d.minside && k_end == d.W - d.target_w && k_end > k_begin) {
             const int tw_px = d.target_w;
-            for (int p = tw; p < P; p += TW) {
-                const int r0 = p * KR, r1 = min(H, r0 + KR), n = r1 - r0;
-                const int rof = lane < n ? *gp(d.ro + r0 + lane) : 0;
+            for (int rc = ra; rc < rb; rc += 64) {
+                const int n = min(64, rb - rc);
+                const int rof = lane < n ? *gp(d.ro + rc + lane) : 0;
 #pragma unroll 1
                 for (int i = 0; i < n; ++i) {
                     const int o = __builtin_amdgcn_readlane(rof, i);
-                    if (o > 0) move_left_wave(d.img + (long long)(r0 + i) * d.pitch, tw_px * d.C, o * d.C, lane);
+                    if (o > 0) move_left_wave(d.img + (long long)(rc + i) * d.pitch, tw_px * d.C, o * d.C, lane);
                 }
             }
             team_sync<TEAM>(d, epoch, G, &sm.flag);
@@ -856,6 +875,7 @@ struct Carver {
     // Carve one image, or (max_seams > 0) continue it by at most max_seams seams.
     static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams) {
         Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        set_prio(d.prio);
         const int nseams = d.mode ? 1 : d.W - d.target_w;
         const int k0 = max_seams > 0 ? (int)ctl->done : 0;
         const int k1 = max_seams > 0 ? min(nseams, k0 + max_seams) : nseams;
@@ -962,14 +982,16 @@ static const Variant kVariants[] = {
     {8, 32, 1024, "cpl8_k32_t1024"},
     {4, 48, 512, "cpl4_k48_t512"},
     {4, 48, 256, "cpl4_k48_t256"},
+    {4, 56, 512, "cpl4_k56_t512"},
 };
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 const Variant& variant(int v) { return kVariants[v]; }
-int default_variant() { return 1; }
-int team_variant() { return 1; }
+int default_variant() { return 7; }
+int team_variant() { return 7; }
 
 #define SC_VARIANTS(X) \
-    X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) X(6, 4, 48, 256)
+    X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) X(6, 4, 48, 256) \
+    X(7, 4, 56, 512)
 
 hipError_t launch_carve_single(const Img& d, int v, int G, hipStream_t st) {
     switch (v) {
