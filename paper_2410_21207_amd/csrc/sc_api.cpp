@@ -64,7 +64,7 @@ size_t ctl_region(int n) { return sc::align_up(sizeof(WsHead) + (size_t)n * size
 // Fill the device descriptor of one image whose scratch starts at `base` and whose Ctl is `ctl`.
 sc::Img make_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
                  int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl, int kr, int G, int mode) {
-    const sc::Layout L = sc::layout_for(H, W, 32);
+    const sc::Layout L = sc::layout_for(H, W, C, 32);
     sc::Img d;
     memset(&d, 0, sizeof(d));
     d.src = src;
@@ -82,6 +82,8 @@ sc::Img make_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long lon
     d.xq = reinterpret_cast<uint32_t*>(base + L.xq);
     d.seam = reinterpret_cast<int32_t*>(base + L.seam);
     d.ro = reinterpret_cast<int32_t*>(base + L.ro);
+    d.wk = reinterpret_cast<uint8_t*>(base + L.wk);
+    d.wp = L.wp;
     d.minside = 1;
     d.amin = &ctl->amin;
     d.bar = &ctl->bar;
@@ -104,7 +106,7 @@ int resolve_variant(const sc_tune* t) {
 
 namespace sc {
 
-Layout layout_for(int H, int W, int kr_min) {
+Layout layout_for(int H, int W, int C, int kr_min) {
     Layout L;
     const int P = (H + kr_min - 1) / kr_min;
     L.P = P;
@@ -125,7 +127,11 @@ Layout layout_for(int H, int W, int kr_min) {
     off = align_up(off + (size_t)H * 4, kAlign);
     L.ro = off;
     off = align_up(off + (size_t)H * 4, kAlign);
-    L.total = off;
+    // working image: 64-byte aligned rows, so a 16-byte slot never spans two rows
+    L.wp = (int)align_up((size_t)W * C, 64);
+    L.wk = off;
+    off = align_up(off + (size_t)H * L.wp, kAlign);
+    L.total = off + kAlign;  // slack: row copies read a few bytes past the last row
     return L;
 }
 
@@ -146,7 +152,7 @@ const char* sc_variant_name(int v) {
 
 size_t sc_workspace_bytes(int H, int W, int C) {
     if (H < 1 || W < 1 || C < 1 || C > 4) return 0;
-    return ctl_region(1) + sc::layout_for(H, W, 32).total;
+    return ctl_region(1) + sc::layout_for(H, W, C, 32).total;
 }
 
 sc_status sc_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t* energy, void* stream) {
@@ -238,7 +244,7 @@ size_t sc_batch_workspace_bytes(const sc_job* jobs, int n) {
     total += sc::align_up((size_t)n * sizeof(int), sc::kAlign);
     for (int i = 0; i < n; ++i) {
         if (jobs[i].H < 1 || jobs[i].W < 1) return 0;
-        total += sc::layout_for(jobs[i].H, jobs[i].W, 32).total;
+        total += sc::layout_for(jobs[i].H, jobs[i].W, jobs[i].C, 32).total;
     }
     return total;
 }
@@ -359,7 +365,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
                            base + off_data, ctl, sc::variant(v).kr, gsz[i], 0);
         if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) imgs[i].minside = 0;
         if (!(tune && (tune->flags & SC_TUNE_NO_PRIO))) imgs[i].prio = prio[i];
-        off_data += sc::layout_for(j.H, j.W, 32).total;
+        off_data += sc::layout_for(j.H, j.W, j.C, 32).total;
         max_rows = std::max(max_rows, j.H);
     }
     memcpy(host.data() + off_blk, blk.data(), blk.size() * sizeof(int2));

@@ -9,8 +9,8 @@ namespace sc {
 
 // Device descriptor of one image being carved.  All pointers are device pointers.
 struct Img {
-    const uint8_t* src;  // optional source copied into img by the energy pass
-    uint8_t* img;        // H rows of `pitch` bytes, carved in place
+    const uint8_t* src;  // optional source (else img is the source)
+    uint8_t* img;        // H rows of `pitch` bytes: receives the carved image
     long long pitch;
     int H, W, C, target_w;
     int32_t* seams_out;  // optional, (W-target_w)*H
@@ -22,10 +22,12 @@ struct Img {
     uint32_t* xq;  // 2 rows of `xw` uint32: DP keys exchanged between waves at phase ends
     int32_t* seam; // current seam, H
     int32_t* ro;   // per row: physical column of the row's first pixel (min-side removal), H
+    uint8_t* wk;   // working copy of the image, H rows of `wp` bytes (64-byte aligned rows)
     unsigned long long* amin;  // packed (cost << 32 | column) argmin of the current seam
     unsigned* bar;             // team barrier counter
     unsigned* status;          // error bits
     int ep, db, xw, P;         // pitches and the number of DP phases
+    int wp;                    // bytes per row of wk
     int G;                     // team size (workgroups) carving this image
     int mode;                  // 0 = carve, 1 = one seam only, no removal (sc_dp_seam)
     int minside;               // 1 = remove a seam pixel by moving the shorter side of its row
@@ -47,8 +49,8 @@ constexpr unsigned kStatusPlacement = 2u;  // a team's workgroups were not on on
 
 // Placement of one image's scratch inside a workspace.
 struct Layout {
-    size_t ctl, e, dirs, anc, xq, seam, ro, total;
-    int ep, db, xw, P;
+    size_t ctl, e, dirs, anc, xq, seam, ro, wk, total;
+    int ep, db, xw, P, wp;
 };
 
 constexpr size_t kAlign = 256;
@@ -63,7 +65,7 @@ struct Variant {
     const char* name;
 };
 
-Layout layout_for(int H, int W, int variant_kr_min);
+Layout layout_for(int H, int W, int C, int variant_kr_min);
 int variant_count();
 const Variant& variant(int v);
 int default_variant();

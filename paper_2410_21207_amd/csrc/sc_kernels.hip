@@ -151,18 +151,24 @@ __device__ __forceinline__ void write_single_header(const Img& d) {
 }
 
 // Per-image preparation: reset the control words, optionally copy src -> img, fill the energy plane.
+// The carve works on the copy in wk; img receives the result at the end (a carve that removes
+// nothing copies src into img here).
 __device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
     const uint8_t* srcimg = d.src ? d.src : d.img;
+    const bool identity = d.src && d.target_w == d.W;
     if (row_begin == 0 && threadIdx.x == 0) reset_ctl(d);
     for (int y = row_begin; y < d.H; y += row_step) {
         if (threadIdx.x == 0) *gp(d.ro + y) = 0;
         uint16_t* er = d.e + (long long)y * d.ep;
+        const uint8_t* s = srcimg + (long long)y * d.pitch;
+        uint8_t* wr = d.wk + (long long)y * d.wp;
+        uint8_t* o = d.img + (long long)y * d.pitch;
         for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
             *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
-            if (d.src) {
-                const uint8_t* s = d.src + (long long)y * d.pitch + (long long)x * d.C;
-                uint8_t* o = d.img + (long long)y * d.pitch + (long long)x * d.C;
-                for (int c = 0; c < d.C; ++c) *gp(o + c) = *gp(s + c);
+            for (int c = 0; c < d.C; ++c) {
+                const uint8_t v = *gp(s + x * d.C + c);
+                *gp(wr + x * d.C + c) = v;
+                if (identity) *gp(o + x * d.C + c) = v;
             }
         }
     }
@@ -287,110 +293,150 @@ __device__ __forceinline__ void shift_segments_wave(uint8_t* a_lo_p, uint8_t* a_
     }
 }
 
-// In-place RIGHT shift of up to two row segments by one pixel, one wave: the bytes of [lo, hi)
-// move to [lo + sh, hi + sh) (min-side removal of a seam pixel from the left part of a row).
-// Slots are processed from the highest address down; a slot's output needs its own 16 bytes and
-// the dword just below it, which belongs to the next lower slot -- loaded in the same pass or a
-// later one, and a pass issues all its loads before its stores, so the update is hazard free.
-template <int U>
-__device__ __forceinline__ void seg_right(uint8_t* lo_p, uint8_t* hi_p, int sh, int fb, int lane, bool load,
-                                          uint32_t (&D)[U][5]) {
-    // destination [lo + sh, hi + sh) in 16-byte slots counted DOWN from the last one
-    const uintptr_t dlo = (uintptr_t)lo_p + sh, dhi = (uintptr_t)hi_p + sh;
-    if (dlo >= dhi) return;
-    const int qoff = (int)(dlo & 15);
-    uint8_t* const base = lo_p + sh - qoff;          // slot-aligned base of the destination
-    const int end = qoff + (int)(dhi - dlo);         // destination as [qoff, end) from base
-    const int n = ((end - 1) >> 4) + 1;
+// One segment of a one-pixel shift inside a row, as 16-byte destination slots aligned to absolute
+// addresses.  Left (R = false): destination [lo, hi) takes the bytes sh above it.  Right (R =
+// true): destination [lo + sh, hi + sh) takes the bytes of [lo, hi).  A slot's output needs its
+// own 16 bytes and one dword beyond it (above for left, below for right) that belongs to the
+// neighbouring slot; slots are numbered so that pass order visits that neighbour in the same
+// pass or a later one (left: ascending addresses, right: descending), and a pass loads before it
+// stores, so the update is hazard free.
+//
+// The row must start on a 16-byte boundary and belong to the calling wave alone while it runs:
+// a slot at either end of the destination is then written whole, with the bytes outside the
+// destination put back as loaded.
+struct SSeg {
+    uint8_t* base;  // 16-byte aligned
+    int q0, q1;     // destination bytes [base + q0, base + q1)
+    int sh;         // shift in bytes, 1..4
+    int n;          // slots
+};
+
+template <bool R>
+__device__ __forceinline__ SSeg sseg(uint8_t* lo, uint8_t* hi, int sh) {
+    SSeg g;
+    uint8_t* dlo = R ? lo + sh : lo;
+    const int off = (int)((uintptr_t)dlo & 15);
+    g.base = dlo - off;
+    g.q0 = off;
+    g.q1 = hi > lo ? off + (int)(hi - lo) : off;
+    g.sh = sh;
+    g.n = g.q1 > g.q0 ? ((g.q1 - 1) >> 4) + 1 : 0;
+    return g;
+}
+
+// W[u] holds 20 loaded bytes: left = the slot then the dword above, right = the dword below then
+// the slot.
+template <int U, bool R>
+__device__ __forceinline__ void sseg_load(const SSeg& g, int fb, int lane, uint32_t (&W)[U][5]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) W[u][i] = 0;
+        const int f = fb + u * 64 + lane;
+        if (f < g.n) {
+            const int so = (R ? g.n - 1 - f : f) << 4;
+            const uint8_t* sp = g.base + so;
+            const uint64_t v0 = *gp(reinterpret_cast<const uint64_t*>(sp));
+            const uint64_t v1 = *gp(reinterpret_cast<const uint64_t*>(sp) + 1);
+            constexpr int k = R ? 1 : 0;
+            W[u][k + 0] = (uint32_t)v0; W[u][k + 1] = (uint32_t)(v0 >> 32);
+            W[u][k + 2] = (uint32_t)v1; W[u][k + 3] = (uint32_t)(v1 >> 32);
+            if (R) {
+                if (so > g.q0 - g.sh) W[u][0] = *gp(reinterpret_cast<const uint32_t*>(sp - 4));
+            } else {
+                if (so + 16 - g.sh < g.q1) W[u][4] = *gp(reinterpret_cast<const uint32_t*>(sp + 16));
+            }
+        }
+    }
+}
+
+template <int U, bool R>
+__device__ __forceinline__ void sseg_store(const SSeg& g, int fb, int lane, const uint32_t (&W)[U][5]) {
+    const int a = R ? 4 - g.sh : g.sh;  // byte offset of the output inside the 20 bytes
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int f = fb + u * 64 + lane;
-        if (f >= n) continue;
-        const int so = (n - 1 - f) << 4;  // slot offset from base, highest slot first
-        uint8_t* sp = base + so;
-        if (load) {
-            const uint64_t* q = reinterpret_cast<const uint64_t*>(sp);
-            const uint64_t v0 = *gp(q), v1 = *gp(q + 1);
-            D[u][1] = (uint32_t)v0; D[u][2] = (uint32_t)(v0 >> 32);
-            D[u][3] = (uint32_t)v1; D[u][4] = (uint32_t)(v1 >> 32);
-            // the dword below the slot is needed when the slot starts above the source start
-            D[u][0] = (uintptr_t)sp > (uintptr_t)lo_p ? *gp(reinterpret_cast<const uint32_t*>(sp - 4)) : 0u;
+        if (f >= g.n) continue;
+        const int so = (R ? g.n - 1 - f : f) << 4;
+        uint32_t o[4];
+        if (a == 4) {
+            o[0] = W[u][1]; o[1] = W[u][2]; o[2] = W[u][3]; o[3] = W[u][4];
         } else {
-            uint32_t o[4];
-            if (sh == 4) {
-                o[0] = D[u][0]; o[1] = D[u][1]; o[2] = D[u][2]; o[3] = D[u][3];
-            } else {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(D[u][i + 1], D[u][i], (uint32_t)(4 - sh));
-            }
-            if (so >= qoff && so + 16 <= end) {
-                *gp(reinterpret_cast<u32x4*>(sp)) = u32x4{o[0], o[1], o[2], o[3]};
-            } else {
-                const int k0 = so > qoff ? 0 : qoff - so;
-                const int k1 = so + 16 < end ? 16 : end - so;
+            for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(W[u][i + 1], W[u][i], (uint32_t)a);
+        }
+        if (so < g.q0 || so + 16 > g.q1) {
+            // an end slot: bytes outside the destination keep the values the pass loaded
+            const int c0 = min(max(g.q0 - so, 0), 16), c1 = min(max(g.q1 - so, 0), 16);
+            const uint32_t m16 = ((1u << c1) - 1u) & ~((1u << c0) - 1u);  // bit k = byte k of the slot
 #pragma unroll
-                for (int k = 0; k < 16; ++k)
-                    if (k >= k0 && k < k1) *gp(sp + k) = (uint8_t)(o[k >> 2] >> ((k & 3) * 8));
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t bm = ((((m16 >> (4 * i)) & 15u) * 0x00204081u) & 0x01010101u) * 0xffu;
+                const uint32_t cur = R ? W[u][i + 1] : W[u][i];
+                o[i] = (o[i] & bm) | (cur & ~bm);
             }
         }
+        *gp(reinterpret_cast<u32x4*>(g.base + so)) = u32x4{o[0], o[1], o[2], o[3]};
     }
 }
 
-template <int U>
-__device__ __forceinline__ void shift_right_segments_wave(uint8_t* a_lo, uint8_t* a_hi, int sh_a, uint8_t* b_lo,
-                                                          uint8_t* b_hi, int sh_b, int lane) {
-    auto slots = [](uint8_t* lo, uint8_t* hi, int sh) {
-        const uintptr_t dlo = (uintptr_t)lo + sh, dhi = (uintptr_t)hi + sh;
-        return dlo < dhi ? (int)((((dlo & 15) + (dhi - dlo)) - 1) >> 4) + 1 : 0;
-    };
-    const int n = max(slots(a_lo, a_hi, sh_a), slots(b_lo, b_hi, sh_b));
+// Two rows' shifts (image and energy segments of row a, then of row b, directions RA and RB)
+// moved together: every pass issues the loads of all four segments before any store, so the
+// rows share each memory round trip.  The segments must not overlap each other's bytes.
+template <int U, bool RA, bool RB>
+__device__ __forceinline__ void shift_rows2_wave(const SSeg& a0, const SSeg& a1, const SSeg& b0, const SSeg& b1,
+                                                 int lane) {
+    const int n = max(max(a0.n, a1.n), max(b0.n, b1.n));
 #pragma unroll 1
     for (int fb = 0; fb < n; fb += 64 * U) {
-        uint32_t DA[U][5], DB[U][5];
-        seg_right<U>(a_lo, a_hi, sh_a, fb, lane, true, DA);
-        seg_right<U>(b_lo, b_hi, sh_b, fb, lane, true, DB);
-        seg_right<U>(a_lo, a_hi, sh_a, fb, lane, false, DA);
-        seg_right<U>(b_lo, b_hi, sh_b, fb, lane, false, DB);
+        uint32_t W0[U][5], W1[U][5], W2[U][5], W3[U][5];
+        sseg_load<U, RA>(a0, fb, lane, W0);
+        sseg_load<U, RA>(a1, fb, lane, W1);
+        sseg_load<U, RB>(b0, fb, lane, W2);
+        sseg_load<U, RB>(b1, fb, lane, W3);
+        sseg_store<U, RA>(a0, fb, lane, W0);
+        sseg_store<U, RA>(a1, fb, lane, W1);
+        sseg_store<U, RB>(b0, fb, lane, W2);
+        sseg_store<U, RB>(b1, fb, lane, W3);
     }
 }
 
-// dst bytes [dst, dst + n) take the values of [dst + sh, dst + sh + n), sh > 0, one wave (moves a
-// row back to column 0 after min-side removal).  Dword-granular: a pass loads its source dwords
-// (ascending, all above everything stored so far) before its stores.
-__device__ __forceinline__ void move_left_wave(uint8_t* dst, int n, int sh, int lane) {
-    if (n <= 0 || sh <= 0) return;
-    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + n;
-    const int off = (int)(d0 & 3);
-    uint8_t* const base = dst - off;                 // dword-aligned; output dword j covers base + 4j
+// dst bytes [dst, dst + n) take the bytes of [src, src + n), one wave; the buffers do not overlap.
+// Dword-granular on the destination; bytes of a destination dword outside [dst, dst + n) are not
+// written (they may belong to a neighbouring row).  Source dwords may be read a few bytes beyond
+// either end of the source range.
+__device__ __forceinline__ void copy_bytes_wave(uint8_t* dst, const uint8_t* src, int n, int lane) {
+    if (n <= 0) return;
+    const int off = (int)((uintptr_t)dst & 3);
+    uint8_t* const base = dst - off;  // dword-aligned; destination dword j covers base + 4j
     const int nd = ((off + n - 1) >> 2) + 1;
-    const uintptr_t s_end = d1 + sh;                 // source bytes end here
-    constexpr int U = 4;
+    const uintptr_t s0 = (uintptr_t)src - (uintptr_t)off;  // source byte of base + x is s0 + x
 #pragma unroll 1
-    for (int jb = 0; jb < nd; jb += 64 * U) {
-        uint32_t lo[U], hi[U];
+    for (int jb = 0; jb < nd; jb += 64 * 4) {
+        uint32_t v[4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int j = jb + u * 64 + lane;
-            lo[u] = hi[u] = 0;
+            v[u] = 0;
             if (j < nd) {
-                const uintptr_t sa = (uintptr_t)base + 4 * j + sh;  // first source byte of dword j
-                const uint32_t* sp = reinterpret_cast<const uint32_t*>(base + ((4 * j + sh) & ~3));
-                lo[u] = *gp(sp);
-                if ((sa & 3) && ((sa & ~(uintptr_t)3) + 4) < s_end) hi[u] = *gp(sp + 1);
+                const uintptr_t sa = s0 + 4 * (uintptr_t)j;
+                const uint32_t* sp = reinterpret_cast<const uint32_t*>(sa & ~(uintptr_t)3);
+                const uint32_t lo = *gp(sp);
+                const uint32_t hi = (sa & 3) ? *gp(sp + 1) : 0u;
+                v[u] = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(sa & 3));
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int j = jb + u * 64 + lane;
             if (j >= nd) continue;
-            const uint32_t v = __builtin_amdgcn_alignbyte(hi[u], lo[u], (uint32_t)((4 * j + sh) & 3));
             uint8_t* dp = base + 4 * j;
-            if ((uintptr_t)dp >= d0 && (uintptr_t)dp + 4 <= d1) {
-                *gp(reinterpret_cast<uint32_t*>(dp)) = v;
+            if (dp >= dst && dp + 4 <= dst + n) {
+                *gp(reinterpret_cast<uint32_t*>(dp)) = v[u];
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if ((uintptr_t)dp + k >= d0 && (uintptr_t)dp + k < d1) *gp(dp + k) = (uint8_t)(v >> (8 * k));
+                    if (dp + k >= dst && dp + k < dst + n) *gp(dp + k) = (uint8_t)(v[u] >> (8 * k));
             }
         }
     }
@@ -811,18 +857,44 @@ struct Carver {
                     // row moves: pixels right of the seam one column left, or pixels left of it one
                     // column right with the row's start offset advanced by one.
                     const int rof = lane >= ia && lane < ib ? *gp(d.ro + r0 + lane) : 0;
-#pragma unroll 1
-                    for (int i = ia; i < ib; ++i) {
-                        const int si = __builtin_amdgcn_readlane(mys, i);  // wave-uniform: scalar addresses
+                    // row i's shift: the shorter side with min-side removal, else the right part
+                    auto right_side = [&](int i) {
+                        const int si = __builtin_amdgcn_readlane(mys, i);
+                        return d.minside && si < w - 1 - si;
+                    };
+                    auto segs = [&](int i, bool R, SSeg& gi, SSeg& ge) {
+                        const int si = __builtin_amdgcn_readlane(mys, i);
                         const int o = __builtin_amdgcn_readlane(rof, i);
-                        uint8_t* row = d.img + (long long)(r0 + i) * d.pitch + (long long)o * d.C;
+                        // rows of wk and of the energy plane start on 64-byte boundaries
+                        uint8_t* row = d.wk + (long long)(r0 + i) * d.wp + (long long)o * d.C;
                         uint8_t* er = reinterpret_cast<uint8_t*>(d.e + (size_t)(r0 + i) * d.ep + o);
-                        if (d.minside && si < w - 1 - si) {
-                            shift_right_segments_wave<4>(row, row + (long long)si * d.C, d.C, er, er + 2 * si, 2, lane);
+                        if (R) {
+                            gi = sseg<true>(row, row + (long long)si * d.C, d.C);
+                            ge = sseg<true>(er, er + 2 * si, 2);
                             if (lane == 0) *gp(d.ro + r0 + i) = o + 1;
                         } else {
-                            shift_segments_wave<4, false>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C,
-                                                         d.C, er + 2 * si, er + 2 * (w - 1), 2, lane);
+                            gi = sseg<false>(row + (long long)si * d.C, row + (long long)(w - 1) * d.C, d.C);
+                            ge = sseg<false>(er + 2 * si, er + 2 * (w - 1), 2);
+                        }
+                    };
+#pragma unroll 1
+                    for (int i = ia; i < ib; i += 2) {  // two rows per memory round trip
+                        const bool two = i + 1 < ib;
+                        const bool ra = right_side(i), rb = two && right_side(i + 1);
+                        SSeg a0, a1, b0, b1;
+                        segs(i, ra, a0, a1);
+                        if (two) {
+                            segs(i + 1, rb, b0, b1);
+                        } else {
+                            b0 = a0; b0.n = 0;
+                            b1 = a1; b1.n = 0;
+                        }
+                        if (ra) {
+                            if (rb) shift_rows2_wave<2, true, true>(a0, a1, b0, b1, lane);
+                            else shift_rows2_wave<2, true, false>(a0, a1, b0, b1, lane);
+                        } else {
+                            if (rb) shift_rows2_wave<2, false, true>(a0, a1, b0, b1, lane);
+                            else shift_rows2_wave<2, false, false>(a0, a1, b0, b1, lane);
                         }
                     }
                 }
@@ -840,9 +912,9 @@ struct Carver {
                     const int s = min(max(ld<TEAM>(d.seam + r), 0), w - 1);
                     const int ru = r > 0 ? r - 1 : 0, rd = r + 1 < H ? r + 1 : H - 1;
                     const int o = ld<TEAM>(d.ro + r);
-                    const uint8_t* pr = d.img + (long long)r * d.pitch + (long long)o * d.C;
-                    const uint8_t* pu = d.img + (long long)ru * d.pitch + (long long)ld<TEAM>(d.ro + ru) * d.C;
-                    const uint8_t* pd = d.img + (long long)rd * d.pitch + (long long)ld<TEAM>(d.ro + rd) * d.C;
+                    const uint8_t* pr = d.wk + (long long)r * d.wp + (long long)o * d.C;
+                    const uint8_t* pu = d.wk + (long long)ru * d.wp + (long long)ld<TEAM>(d.ro + ru) * d.C;
+                    const uint8_t* pd = d.wk + (long long)rd * d.wp + (long long)ld<TEAM>(d.ro + rd) * d.C;
                     uint16_t* er = d.e + (size_t)r * d.ep + o;
                     if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s - 1);
                     if (s < w2) *gp(er + s) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s);
@@ -856,16 +928,17 @@ struct Carver {
                 ctl->t_stage[2] += tm3 - tm2;
             }
         }
-        // ---- after the last seam, move rows carved from the left back to column 0
-        if (!d.mode && d.minside && k_end == d.W - d.target_w && k_end > k_begin) {
-            const int tw_px = d.target_w;
+        // ---- after the last seam, the carved rows go from wk (each from its start offset) to img
+        if (!d.mode && k_end == d.W - d.target_w && k_end > k_begin) {
+            const int nb = d.target_w * d.C;
             for (int rc = ra; rc < rb; rc += 64) {
                 const int n = min(64, rb - rc);
                 const int rof = lane < n ? *gp(d.ro + rc + lane) : 0;
 #pragma unroll 1
                 for (int i = 0; i < n; ++i) {
                     const int o = __builtin_amdgcn_readlane(rof, i);
-                    if (o > 0) move_left_wave(d.img + (long long)(rc + i) * d.pitch, tw_px * d.C, o * d.C, lane);
+                    copy_bytes_wave(d.img + (long long)(rc + i) * d.pitch, d.wk + (long long)(rc + i) * d.wp + (long long)o * d.C,
+                                    nb, lane);
                 }
             }
             team_sync<TEAM>(d, epoch, G, &sm.flag);
