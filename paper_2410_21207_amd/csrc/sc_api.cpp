@@ -118,7 +118,7 @@ Layout layout_for(int H, int W, int C, int kr_min) {
     L.e = off;
     off = align_up(off + (size_t)H * L.ep * 2, kAlign);
     L.dirs = off;
-    off = align_up(off + (size_t)H * L.db, kAlign);
+    off = align_up(off + (size_t)align_up((size_t)H, 4) * L.db, kAlign);  // rows grouped by four
     L.anc = off;
     off = align_up(off + (size_t)P * W, kAlign);
     L.xq = off;

@@ -151,12 +151,21 @@ __device__ __forceinline__ void write_single_header(const Img& d) {
 }
 
 // Per-image preparation: reset the control words, optionally copy src -> img, fill the energy plane.
+// Zero both DP exchange rows: a published key carries its phase's tag (never 0), so nothing a
+// previous launch left there can pass for a key of this one.
+__device__ __forceinline__ void clear_exchange(const Img& d) {
+    for (int x = threadIdx.x; x < 2 * d.xw; x += blockDim.x) *gp(d.xq + x) = 0u;
+}
+
 // The carve works on the copy in wk; img receives the result at the end (a carve that removes
 // nothing copies src into img here).
 __device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
     const uint8_t* srcimg = d.src ? d.src : d.img;
     const bool identity = d.src && d.target_w == d.W;
-    if (row_begin == 0 && threadIdx.x == 0) reset_ctl(d);
+    if (row_begin == 0) {
+        if (threadIdx.x == 0) reset_ctl(d);
+        clear_exchange(d);
+    }
     for (int y = row_begin; y < d.H; y += row_step) {
         if (threadIdx.x == 0) *gp(d.ro + y) = 0;
         uint16_t* er = d.e + (long long)y * d.ep;
@@ -189,9 +198,12 @@ __global__ void prepare_batch_kernel(const Img* __restrict__ imgs, int n) {
 
 // Energy plane from a caller's int32 energy map (sc_dp_seam).
 __global__ void prepare_from_i32_kernel(Img d, const int32_t* __restrict__ e) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-        write_single_header(d);
-        reset_ctl(d);
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (threadIdx.x == 0) {
+            write_single_header(d);
+            reset_ctl(d);
+        }
+        clear_exchange(d);
     }
     const int y = blockIdx.y;
     if (blockIdx.x == 0 && threadIdx.x == 0) *gp(d.ro + y) = 0;
@@ -618,9 +630,15 @@ struct Carver {
     // the first PF rows of the wave's next item `nx`, so the energy stream runs across phase
     // boundaries.  The row loop has no lane-dependent branches: every load targets a valid row and
     // column, and lanes that do not own their columns store their directions to a dropped offset.
+    // Tag of the keys published at global phase g (seam k, phase p: g = k * P + p): 1..511, never
+    // the 0 of a cleared exchange row.  Two phases apart the tags differ, which is all a reader
+    // of the double-buffered rows needs.
+    static __device__ __forceinline__ uint32_t phase_tag(int g) { return 1u + (uint32_t)g % 511u; }
+
+    // Returns false when the wait for a neighbour's keys timed out (the image's status says so).
     template <bool EDGE, bool TEAM>
-    static __device__ __forceinline__ void dp_item(const Img& d, Smem& sm, int w, int p, int t, int lane,
-                                                   EV (&ring)[PF], bool preloaded, const Next& nx) {
+    static __device__ __forceinline__ bool dp_item(const Img& d, Smem& sm, int w, int p, int t, int lane,
+                                                   EV (&ring)[PF], bool preloaded, const Next& nx, int gk) {
         const int r0 = __builtin_amdgcn_readfirstlane(p * KR), r1 = min(d.H, r0 + KR);
         const int base = t * S - KR;
         const int col0 = base + lane * CPL;
@@ -633,7 +651,7 @@ struct Carver {
         const uint32_t eoff = (uint32_t)(lane_any ? col0 : 0) * 2u;  // lanes off the image read column 0
         const uint32_t erb = (uint32_t)d.ep * 2u;                       // bytes per energy row
         const __amdgpu_buffer_rsrc_t re = make_rsrc(d.e, (uint32_t)d.H * erb);
-        const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)d.H * (uint32_t)d.db);
+        const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)((d.H + 3) & ~3) * (uint32_t)d.db);
         // start offsets of this item's rows and of the next item's rows: lane l holds row r0 + l
         const int last = d.H - 1;
         const int rov = lane < KR ? ld<TEAM>(d.ro + min(r0 + lane, last)) : 0;
@@ -661,12 +679,36 @@ struct Carver {
             const int cx = lane_any ? col0 : 0;
             uint32_t x[CPL];
             if constexpr (TEAM) {
+                // The keys of phase p - 1 come from this strip and its two neighbours, which publish
+                // them with the phase's tag in the low 9 bits (the offset and direction bits that
+                // the DP resets here anyway); wait until every valid column shows that tag.
                 const uint64_t* xr = reinterpret_cast<const uint64_t*>(d.xq + (size_t)((p - 1) & 1) * d.xw + cx);
+                const uint32_t want = phase_tag(gk + p - 1);
+                unsigned long long t0 = 0;
+                for (int it = 0;; ++it) {
 #pragma unroll
-                for (int i = 0; i < CPL / 2; ++i) {
-                    const uint64_t v = ld<true>(xr + i);
-                    x[2 * i] = (uint32_t)v;
-                    x[2 * i + 1] = (uint32_t)(v >> 32);
+                    for (int i = 0; i < CPL / 2; ++i) {
+                        const uint64_t v = ld<true>(xr + i);
+                        x[2 * i] = (uint32_t)v;
+                        x[2 * i + 1] = (uint32_t)(v >> 32);
+                    }
+                    bool ok = true;
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) ok = ok && (!valid[k] || (x[k] & 0x1FFu) == want);
+                    if (__all(ok)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((it & 63) == 63) {  // bounded wait: 10 s at the 100 MHz constant clock
+                        const unsigned long long now = wall_clock64();
+                        if (t0 == 0) t0 = now;
+                        if (now - t0 > 1000000000ull ||
+                            (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                             (kStatusTimeout | kStatusPlacement))) {
+                            if (lane == 0)
+                                __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                            return false;
+                        }
+                    }
                 }
             } else {
                 const uint32_t* xr = &sm.xs[(p - 1) & 1][cx];
@@ -677,24 +719,38 @@ struct Carver {
             for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? (x[k] & ~0x1FFu) : QINF;  // offset and tag reset
         }
         const bool cross = nx.valid && ((r1 - r0) % PF == 0);
-        // byte of the lane's directions in a row; lanes that do not own their columns store to a
-        // dropped offset instead of branching around the store
-        const uint32_t doff = owned ? (uint32_t)(col0 >> 2) : kBufDrop;
-        const uint32_t db = (uint32_t)d.db;
+        // The direction map groups rows by four: the dword at ((r >> 2) * db + b) * 4 holds the
+        // direction byte b (4 columns, 2 bits each) of rows r & ~3 .. (r & ~3) + 3, lowest row in
+        // the lowest byte.  A lane gathers its bytes of a group in registers and stores them once;
+        // lanes that do not own their columns store to a dropped offset instead of branching.
+        const uint32_t doff = owned ? (uint32_t)(col0 >> 2) * 4u : kBufDrop;
+        const uint32_t gbytes = (uint32_t)d.db * 4u;  // bytes per 4-row group
+        uint32_t pk0 = 0, pk1 = 0;                    // CPL 8: pk1 holds the lane's second byte
 
+        auto flush = [&](int r) {  // r: the last row gathered; stores the group of row r
+            const int sh = 8 * (3 - (r & 3));          // a partial group sits in the top bytes
+            if constexpr (CPL == 4) {
+                __builtin_amdgcn_raw_buffer_store_b32(pk0 >> sh, rdir, (int)doff, (int)((uint32_t)(r >> 2) * gbytes), 0);
+            } else {
+                const v2u v = {pk0 >> sh, pk1 >> sh};
+                __builtin_amdgcn_raw_buffer_store_b64(v, rdir, (int)doff, (int)((uint32_t)(r >> 2) * gbytes), 0);
+            }
+        };
         auto step = [&](int r, const EV& ev) {
             const uint32_t acc = row_step(Q, ev);
             if (EDGE) {
 #pragma unroll
                 for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
             }
-            if constexpr (CPL == 4)
-                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(acc >> 24), rdir, (int)doff, (int)((uint32_t)r * db), 0);
-            else
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(acc >> 16), rdir, (int)doff, (int)((uint32_t)r * db), 0);
+            if constexpr (CPL == 4) {
+                pk0 = (pk0 >> 8) | (acc & 0xFF000000u);
+            } else {
+                pk0 = (pk0 >> 8) | ((acc << 8) & 0xFF000000u);
+                pk1 = (pk1 >> 8) | (acc & 0xFF000000u);
+            }
         };
 
-        int rb = r0;
+        int rb = r0;  // r0 and every block start are multiples of 4, so groups never straddle blocks
         // blocks whose prefetch targets stay inside this item
         for (; rb + 2 * PF <= r1; rb += PF) {
 #pragma unroll
@@ -702,6 +758,7 @@ struct Carver {
                 const EV ev = ring[i];
                 ring[i] = load_ev<TEAM>(re, soff(rb - r0 + i + PF), eoff);
                 step(rb + i, ev);
+                if ((i & 3) == 3) flush(rb + i);
             }
         }
         // the last full block prefetches the next item's first rows, or else this item's partial
@@ -713,20 +770,26 @@ struct Carver {
                 ring[i] = load_ev<TEAM>(re, cross ? soffn(i) : soff(min(rb - r0 + PF + i, r1 - 1 - r0)),
                                         cross ? nx.off : eoff);
                 step(rb + i, ev);
+                if ((i & 3) == 3) flush(rb + i);
             }
             rb += PF;
         }
         // the rows of a partial last phase (the next item then loads its own first rows)
 #pragma unroll
-        for (int i = 0; i < PF; ++i)
-            if (rb + i < r1) step(rb + i, ring[i]);
+        for (int i = 0; i < PF; ++i) {
+            if (rb + i < r1) {
+                step(rb + i, ring[i]);
+                if ((i & 3) == 3 || rb + i == r1 - 1) flush(rb + i);
+            }
+        }
 
         // phase end: publish the last row of the owned columns and their ancestor offsets
         if (owned) {
             if constexpr (TEAM) {
                 uint32_t* xw = d.xq + (size_t)(p & 1) * d.xw + col0;
+                const uint32_t tag = phase_tag(gk + p);
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) *gp(xw + k) = Q[k];
+                for (int k = 0; k < CPL; ++k) *gp(xw + k) = (Q[k] & ~0x1FFu) | tag;
             } else {
                 uint32_t* xw = &sm.xs[p & 1][col0];
 #pragma unroll
@@ -755,6 +818,7 @@ struct Carver {
             }
             if (lane == 0 && key != ~0ull) atomicMin(d.amin, key);
         }
+        return true;
     }
 
     // Seams k_begin .. k_end-1 of one image (the image has W - k_begin columns on entry).
@@ -790,10 +854,18 @@ struct Carver {
                     const int tn = j + 1 < nsw ? t + TW : tw;
                     const Next nx = make_next(d, w, pn, tn, lane, !last);
                     const int base = t * S - KR;
-                    if (base < 0 || base + WIN > w) dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx);
-                    else dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx);
+                    const bool ok = (base < 0 || base + WIN > w)
+                                        ? dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P)
+                                        : dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P);
+                    if (!ok) return;
                     preloaded = nx.valid && ((min(H, p * KR + KR) - p * KR) % PF == 0);
                 }
+                // one workgroup exchanges phase ends through LDS behind a barrier; a team's waves
+                // wait only for the tagged keys of their neighbours (in dp_item)
+                if constexpr (!TEAM) __syncthreads();
+            }
+            // the directions, ancestor offsets and argmin of every phase are complete past here
+            if constexpr (TEAM) {
                 if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
             }
             if (timer) tm1 = wall_clock64();
@@ -822,13 +894,27 @@ struct Carver {
                 while (__hip_atomic_load(&sm.chain, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > p)
                     __builtin_amdgcn_s_sleep(1);
                 const int je = sm.jend[p];
-                const int dlo = (max(0, je - KR) >> 2) >> 2;
-                const int ndw = d.db >> 2;
+                // the walk stays within KR columns of je: direction bytes cb0 .. cb0 + GW - 1 of
+                // every 4-row group of the phase, kept in LDS as [group][byte]
+                constexpr int GW = 4 * WD;
+                const int cb0 = max(0, je - KR) >> 2;
                 uint32_t* win = sm.win[wv];
-                if (lane >= ia && lane < n) {
-                    const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs + (size_t)(r0 + lane) * d.db);
+                {
+                    // all of a lane's loads are issued before its LDS writes (one memory round trip)
+                    constexpr int NI = (KR / 4 * GW + 63) / 64;
+                    const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs) + (size_t)(r0 >> 2) * d.db;
+                    const int g0 = ia >> 2, nx = (((n + 3) >> 2) - g0) * GW;  // groups holding rows ia .. n-1
+                    uint32_t v[NI];
 #pragma unroll
-                    for (int q = 0; q < WD; ++q) win[lane * WD + q] = (dlo + q < ndw) ? ld<TEAM>(src + dlo + q) : 0u;
+                    for (int j = 0; j < NI; ++j) {
+                        const int x = lane + 64 * j, g = g0 + x / GW, q = x % GW;
+                        v[j] = x < nx && cb0 + q < d.db ? ld<TEAM>(src + (size_t)g * d.db + cb0 + q) : 0u;
+                    }
+#pragma unroll
+                    for (int j = 0; j < NI; ++j) {
+                        const int x = lane + 64 * j;
+                        if (x < nx) win[(g0 + x / GW) * GW + x % GW] = v[j];
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -837,10 +923,9 @@ struct Carver {
                 for (int i = n - 1; i >= ia; --i) {
                     if (lane == i) mys = s;
                     if (i > 0) {
-                        const int b = s >> 2;
-                        const int q = min(max((b >> 2) - dlo, 0), WD - 1);
-                        const uint32_t wd = win[i * WD + q];
-                        s += (int)((wd >> ((b & 3) * 8 + (s & 3) * 2)) & 3u) - 1;
+                        const int q = min(max((s >> 2) - cb0, 0), GW - 1);
+                        const uint32_t wd = win[(i >> 2) * GW + q];
+                        s += (int)((wd >> ((i & 3) * 8 + (s & 3) * 2)) & 3u) - 1;
                         s = min(max(s, 0), w - 1);
                     }
                 }
@@ -1040,7 +1125,7 @@ __global__ void unpack_dirs_kernel(Img d, uint8_t* __restrict__ out) {
     const int y = blockIdx.y;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < d.W; x += gridDim.x * blockDim.x) {
         uint8_t v = 1;
-        if (y > 0) v = (*gp(d.dirs + (size_t)y * d.db + (x >> 2)) >> ((x & 3) * 2)) & 3u;
+        if (y > 0) v = (*gp(d.dirs + ((size_t)(y >> 2) * d.db + (x >> 2)) * 4 + (y & 3)) >> ((x & 3) * 2)) & 3u;
         *gp(out + (size_t)y * d.W + x) = v;
     }
 }
