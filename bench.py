@@ -219,7 +219,8 @@ def main():
                                "10-40% of width removed (seed 3)",
                    "images": len(jobs), "seams": seams_total, "pixel_seams": pixel_seams,
                    "team": bc.info.team, "variant": api.variants()[bc.info.variant], "minside": minside,
-                   "prio": not args.no_prio},
+                   "prio": not args.no_prio, "autotuned": args.team is None and args.variant is None
+                   and bc.tuned != (None, None)},
         "roofline": roofline,
         "hbm_gbps_step": round(model_bytes / (ms_per_step / 1000.0) / 1e9, 1),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),

@@ -92,6 +92,19 @@ def transpose(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -
     return out
 
 
+_arch: dict = {}
+
+
+def _tuned(device, key_fn):
+    """(variant, team) the autotuner recorded for this device and size bucket, else (None, None)."""
+    from . import tune
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    if idx not in _arch:
+        _arch[idx] = tune.device_arch(idx)
+    hit = tune.lookup(key_fn(_arch[idx]))
+    return hit if hit else (None, None)
+
+
 def _tune(team=None, variant=None, minside=True):
     if team is None and variant is None and minside:
         return None
@@ -111,6 +124,9 @@ def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, rec
         sH, sW, sC, spitch = _image(src, "src")
         if (sH, sW, sC, spitch) != (H, W, C, pitch):
             raise ValueError("src must have the shape and pitch of img")
+    if team is None and variant is None:  # the autotuner's choice for this size, if any
+        from . import tune
+        variant, team = _tuned(img.device, lambda a: tune.key_single(a, H, W))
     k = W - int(target_w)
     lib = _lib.load()
     need = lib.sc_workspace_bytes(H, W, C)
@@ -207,6 +223,11 @@ class BatchCarver:
             costs = torch.empty(k, dtype=torch.int64, device=img.device) if record and k > 0 else None
             self.jobs.append(_Job(src, img, int(tw), seams, costs))
         n = len(self.jobs)
+        if team is None and variant is None:  # the autotuner's choice for this batch shape, if any
+            from . import tune
+            shapes = [(j.img.shape[0], j.img.shape[1]) for j in self.jobs]
+            variant, team = _tuned(self.jobs[0].img.device, lambda a: tune.key_batch(a, shapes))
+        self.tuned = (variant, team)
         self._cjobs = (_lib.sc_job * n)()
         for i, j in enumerate(self.jobs):
             H, W, C, pitch = _image(j.img)
