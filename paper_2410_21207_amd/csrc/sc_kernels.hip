@@ -637,8 +637,11 @@ struct Carver {
 
     // Returns false when the wait for a neighbour's keys timed out (the image's status says so).
     template <bool EDGE, bool TEAM>
+    // `rovc` carries the row start offsets of the next item (lane l: its row l) from one item to
+    // the next together with the prefetched energy rows.
     static __device__ __forceinline__ bool dp_item(const Img& d, Smem& sm, int w, int p, int t, int lane,
-                                                   EV (&ring)[PF], bool preloaded, const Next& nx, int gk) {
+                                                   EV (&ring)[PF], bool preloaded, const Next& nx, int gk,
+                                                   int& rovc) {
         const int r0 = __builtin_amdgcn_readfirstlane(p * KR), r1 = min(d.H, r0 + KR);
         const int base = t * S - KR;
         const int col0 = base + lane * CPL;
@@ -652,19 +655,19 @@ struct Carver {
         const uint32_t erb = (uint32_t)d.ep * 2u;                       // bytes per energy row
         const __amdgpu_buffer_rsrc_t re = make_rsrc(d.e, (uint32_t)d.H * erb);
         const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)((d.H + 3) & ~3) * (uint32_t)d.db);
-        // start offsets of this item's rows and of the next item's rows: lane l holds row r0 + l
+        // start offsets of this item's rows and of the next item's rows: lane l holds row r0 + l.
+        // A preloaded item got its own from the previous item, so its first prefetch does not wait.
         const int last = d.H - 1;
-        const int rov = lane < KR ? ld<TEAM>(d.ro + min(r0 + lane, last)) : 0;
+        const int rov = preloaded ? rovc : lane < KR ? ld<TEAM>(d.ro + min(r0 + lane, last)) : 0;
         const int rovn = lane < KR ? ld<TEAM>(d.ro + min(nx.r0 + lane, last)) : 0;
-        // byte offset of row r0 + i of this item (i < KR), wave-uniform
-        auto soff = [&](int i) {
-            const int r = min(r0 + i, last);
-            return (uint32_t)r * erb + 2u * (uint32_t)__builtin_amdgcn_readlane(rov, r - r0);
-        };
-        auto soffn = [&](int i) {
-            const int r = min(nx.r0 + i, last);
-            return (uint32_t)r * erb + 2u * (uint32_t)__builtin_amdgcn_readlane(rovn, r - nx.r0);
-        };
+        rovc = rovn;
+        // byte offset in the energy plane of row r0 + l (row base plus the row's start offset) in
+        // lane l, rows past the image clamped to the last one; a row's scalar buffer offset is
+        // then one readlane
+        const uint32_t roff = (uint32_t)min(r0 + lane, last) * erb + 2u * (uint32_t)rov;
+        const uint32_t roffn = (uint32_t)min(nx.r0 + lane, last) * erb + 2u * (uint32_t)rovn;
+        auto soff = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane(roff, i); };    // i < KR
+        auto soffn = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane(roffn, i); };  // i < PF
         if (!preloaded) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) ring[i] = load_ev<TEAM>(re, soff(i), eoff);
@@ -742,11 +745,13 @@ struct Carver {
 #pragma unroll
                 for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
             }
+            // shift the group's bytes down one and put this row's byte on top: one v_perm_b32
+            // (selector bytes 0-3 pick from pk, 4-7 from acc)
             if constexpr (CPL == 4) {
-                pk0 = (pk0 >> 8) | (acc & 0xFF000000u);
+                pk0 = __builtin_amdgcn_perm(acc, pk0, 0x07030201u);
             } else {
-                pk0 = (pk0 >> 8) | ((acc << 8) & 0xFF000000u);
-                pk1 = (pk1 >> 8) | (acc & 0xFF000000u);
+                pk0 = __builtin_amdgcn_perm(acc, pk0, 0x06030201u);
+                pk1 = __builtin_amdgcn_perm(acc, pk1, 0x07030201u);
             }
         };
 
@@ -754,10 +759,9 @@ struct Carver {
         // blocks whose prefetch targets stay inside this item
         for (; rb + 2 * PF <= r1; rb += PF) {
 #pragma unroll
-            for (int i = 0; i < PF; ++i) {
-                const EV ev = ring[i];
+            for (int i = 0; i < PF; ++i) {  // the slot is refilled after its row (no register copy)
+                step(rb + i, ring[i]);
                 ring[i] = load_ev<TEAM>(re, soff(rb - r0 + i + PF), eoff);
-                step(rb + i, ev);
                 if ((i & 3) == 3) flush(rb + i);
             }
         }
@@ -766,10 +770,9 @@ struct Carver {
         if (rb + PF <= r1) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
-                const EV ev = ring[i];
+                step(rb + i, ring[i]);
                 ring[i] = load_ev<TEAM>(re, cross ? soffn(i) : soff(min(rb - r0 + PF + i, r1 - 1 - r0)),
                                         cross ? nx.off : eoff);
-                step(rb + i, ev);
                 if ((i & 3) == 3) flush(rb + i);
             }
             rb += PF;
@@ -843,6 +846,7 @@ struct Carver {
             const int nsw = tw < nstr ? (nstr - tw + TW - 1) / TW : 0;  // strips of this wave per phase
             EV ring[PF];
             bool preloaded = false;
+            int rovc = 0;
             // no phase end of this seam is known yet; the DP's barriers order this reset before
             // any walker of this seam reads it, and after every walker of the previous seam
             if (threadIdx.x == 0) sm.chain = 0x7fffffff;
@@ -855,8 +859,8 @@ struct Carver {
                     const Next nx = make_next(d, w, pn, tn, lane, !last);
                     const int base = t * S - KR;
                     const bool ok = (base < 0 || base + WIN > w)
-                                        ? dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P)
-                                        : dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P);
+                                        ? dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P, rovc)
+                                        : dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P, rovc);
                     if (!ok) return;
                     preloaded = nx.valid && ((min(H, p * KR + KR) - p * KR) % PF == 0);
                 }
