@@ -18,6 +18,7 @@ import argparse
 import ctypes
 import json
 import math
+import sys
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -151,16 +152,24 @@ class Server:
         return not self.queue and not self.active
 
     # ------------------------------------------------------------------ open-loop run
-    def run(self, arrivals, make_payload, horizon: float | None = None, sleep=time.sleep):
+    def run(self, arrivals, make_payload, horizon: float | None = None, sleep=time.sleep, progress=None,
+            progress_every: float = 5.0):
         """Serve `arrivals` (objects with .t, .h, .w, .target_w) released at their arrival times.
 
-        make_payload(req) builds a request's pixels when it arrives.  Returns self.stats().
+        make_payload(req) builds a request's pixels when it arrives.  progress(text), when given,
+        is called about every `progress_every` seconds.  Returns self.stats().
         """
         arrivals = sorted(arrivals, key=lambda r: r.t)
         t0 = self.clock()
         i = 0
+        next_report = progress_every
         while i < len(arrivals) or not self.idle():
             now = self.clock() - t0
+            if progress is not None and now >= next_report:
+                next_report += progress_every
+                done = sum(t.status == "done" for t in self.tickets)
+                progress(f"t={now:.1f}s arrived {i}/{len(arrivals)} active {len(self.active)} "
+                         f"queued {len(self.queue)} done {done} steps {self.steps}")
             while i < len(arrivals) and arrivals[i].t <= now:
                 r = arrivals[i]
                 self.submit(r.h, r.w, getattr(r, "c", 3), r.target_w, make_payload(r), arrival=t0 + r.t)
@@ -272,7 +281,7 @@ def main():
 
     srv = Server(GPUExecutor(args.slots, dev), budget_bytes=int(args.budget_gb * 1e9), max_slots=args.slots,
                  seams_per_step=args.seams_per_step)
-    st = srv.run(reqs, payload)
+    st = srv.run(reqs, payload, progress=lambda m: print(m, file=sys.stderr, flush=True))
     offered = sum(r.h * ((r.w - r.target_w) * r.w - (r.w - r.target_w) * (r.w - r.target_w - 1) // 2)
                   for r in reqs) / args.duration
     st.update({"workload": f"Poisson {args.rate}/s for {args.duration}s, sides log-uniform [128,4096], "
