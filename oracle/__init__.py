@@ -71,6 +71,8 @@ class Oracle:
             "sco_carve": [P, I, I, I, I, I, P, P],
             "sco_transpose": [P, I, I, I, I, P, I],
             "sco_carve_hv": [P, I, I, I, I, I, I, P, I, P, P, P, P],
+            "sco_seam_origins": [P, I, I, I, P],
+            "sco_insert_seams": [P, I, I, I, I, I, P, I, P],
             "sco_greedy_seam": [P, I, I, P, P],
             "sco_brute_seam": [P, I, I, P, P],
         }
@@ -146,6 +148,23 @@ class Oracle:
                                      _p(vs), _p(vc), _p(hs), _p(hc)), "carve_hv")
         return out, vs, vc, hs, hc
 
+    def seam_origins(self, seams, W: int) -> np.ndarray:
+        """Original columns of seams recorded in current coordinates ([k, H] int32)."""
+        seams = np.ascontiguousarray(seams, dtype=np.int32)
+        k, H = seams.shape
+        orig = np.zeros((k, H), dtype=np.int32)
+        _check(self.lib.sco_seam_origins(_p(seams), k, H, W, _p(orig)), "seam_origins")
+        return orig
+
+    def insert_seams(self, img, k: int):
+        """Widen img by k seams: (out [H, W + k, C], original seam columns [k, H])."""
+        img = _img(img)
+        H, W, C = img.shape
+        out = np.zeros((H, W + k, C), dtype=np.uint8)
+        orig = np.zeros((max(k, 1), H), dtype=np.int32)
+        _check(self.lib.sco_insert_seams(_p(img), H, W, C, W * C, k, _p(out), (W + k) * C, _p(orig)), "insert_seams")
+        return out, orig[:k]
+
     def greedy_seam(self, e):
         """Alg. 2 greedy seam of an int32 [H, W] energy map -> (seam, cost)."""
         e = np.ascontiguousarray(np.asarray(e, dtype=np.int32))
@@ -194,6 +213,14 @@ def transpose(img):
 
 def carve_hv(img, target_w: int, target_h: int):
     return default().carve_hv(img, target_w, target_h)
+
+
+def seam_origins(seams, W: int):
+    return default().seam_origins(seams, W)
+
+
+def insert_seams(img, k: int):
+    return default().insert_seams(img, k)
 
 
 def greedy_seam(e):

@@ -34,6 +34,13 @@
  *       the energy recomputed after every removal.
  *   R10 horizontal seams (sec. "Design Techniques", reduction by swapping
  *       rows and columns): a plain transpose, vertical seams first.
+ *   R15 seam insertion (sec. "Image Enlargement"): the k seams are found by
+ *       removal on a copy; in the original image the recorded seams are k
+ *       distinct pixels per row, so inserting the seams one by one in removal
+ *       order puts one new pixel immediately right of each recorded pixel.
+ *   R16 value of an inserted pixel ("average of the left/right neighbours"):
+ *       (a + b + 1) >> 1 per channel, a = the recorded pixel, b = its right
+ *       neighbour in the original image (a itself at the last column).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -167,6 +174,81 @@ int sco_carve(uint8_t* img, int H, int W, int C, int pitch, int target_w, int32_
     }
     free(e);
     free(s);
+    return rc;
+}
+
+/*
+ * Original columns of removed seams (sec. "Image Enlargement", R15).  seams:
+ * k*H int32 in the coordinates of the image each seam was removed from (as
+ * sco_carve records them); orig: k*H int32, the same seams as columns of the
+ * image before any removal.  Per row, a list of the original columns still
+ * present is kept and each seam takes out the entry it points at.
+ */
+int sco_seam_origins(const int32_t* seams, int k, int H, int W, int32_t* orig) {
+    if ((k > 0 && (!seams || !orig)) || k < 0 || k >= W || H < 1 || W < 1) return SCO_EINVAL;
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)W);
+    if (!idx) return SCO_ENOMEM;
+    int rc = SCO_OK;
+    for (int r = 0; r < H && rc == SCO_OK; ++r) {
+        for (int x = 0; x < W; ++x) idx[x] = x;
+        for (int j = 0, w = W; j < k; ++j, --w) {
+            int s = seams[(size_t)j * H + r];
+            if (s < 0 || s >= w) {
+                rc = SCO_EINVAL;
+                break;
+            }
+            orig[(size_t)j * H + r] = idx[s];
+            memmove(idx + s, idx + s + 1, sizeof(int32_t) * (size_t)(w - 1 - s));
+        }
+    }
+    free(idx);
+    return rc;
+}
+
+/*
+ * Seam insertion (sec. "Image Enlargement", R15, R16): widen img (H x W x C)
+ * by k columns.  The k minimum seams are found by carving a copy (R9), mapped
+ * to original columns, and a new pixel is placed right of each recorded pixel.
+ * out: H rows of out_pitch bytes, (W + k) * C used.  orig_out: nullable, k*H
+ * int32, the seams' original columns in removal order.  0 <= k < W.
+ */
+int sco_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, int k, uint8_t* out, int out_pitch,
+                     int32_t* orig_out) {
+    if (!img || !out || H < 1 || W < 1 || C < 1 || pitch < W * C || k < 0 || k >= W ||
+        out_pitch < (W + k) * C)
+        return SCO_EINVAL;
+    uint8_t* tmp = (uint8_t*)malloc((size_t)H * W * C);
+    int32_t* seams = (int32_t*)malloc(sizeof(int32_t) * ((size_t)k * H + 1));
+    int32_t* orig = (int32_t*)malloc(sizeof(int32_t) * ((size_t)k * H + 1));
+    uint8_t* mark = (uint8_t*)malloc((size_t)W);
+    int rc = (tmp && seams && orig && mark) ? SCO_OK : SCO_ENOMEM;
+    if (rc == SCO_OK) {
+        for (int y = 0; y < H; ++y) memcpy(tmp + (size_t)y * W * C, img + (size_t)y * pitch, (size_t)W * C);
+        if (k > 0) rc = sco_carve(tmp, H, W, C, W * C, W - k, seams, NULL);
+        if (rc == SCO_OK && k > 0) rc = sco_seam_origins(seams, k, H, W, orig);
+    }
+    for (int y = 0; y < H && rc == SCO_OK; ++y) {
+        const uint8_t* row = img + (size_t)y * pitch;
+        uint8_t* o = out + (size_t)y * out_pitch;
+        memset(mark, 0, (size_t)W);
+        for (int j = 0; j < k; ++j) mark[orig[(size_t)j * H + y]] = 1;
+        int p = 0;
+        for (int x = 0; x < W; ++x) {
+            for (int c = 0; c < C; ++c) o[(size_t)p * C + c] = row[(size_t)x * C + c];
+            ++p;
+            if (mark[x]) {
+                int xr = clampi(x + 1, 0, W - 1);
+                for (int c = 0; c < C; ++c)
+                    o[(size_t)p * C + c] = (uint8_t)((row[(size_t)x * C + c] + row[(size_t)xr * C + c] + 1) >> 1);
+                ++p;
+            }
+        }
+    }
+    if (rc == SCO_OK && orig_out && k > 0) memcpy(orig_out, orig, sizeof(int32_t) * (size_t)k * H);
+    free(tmp);
+    free(seams);
+    free(orig);
+    free(mark);
     return rc;
 }
 

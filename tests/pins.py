@@ -256,3 +256,100 @@ def pin_carve_hv(o):
 
 ALL_PINS = [pin_hand_grids, pin_pixel_grid, pin_bruteforce, pin_energy_closed_forms, pin_energy_symmetry,
             pin_carve_closed_forms, pin_carve_invariants, pin_carve_hv]
+
+
+# --------------------------------------------------------------------------------------------
+# Seam insertion (sec. "Image Enlargement"; readings R15, R16)
+
+def py_insert_sequential(img, seams_cur):
+    """The paper's process, written independently of the oracle: the recorded seams are inserted
+    one by one in removal order, each next to its own pixels.  A seam's pixel in a row is found by
+    replaying the removals on a list of original columns; the growing row is a list of (original
+    column, value) entries searched for that pixel, and the new entry goes right after it with
+    (a + b + 1) >> 1 of the pixel and the entry that follows it (the pixel itself at the right
+    border).  (Shifting every later seam by 2 at or right of each inserted one, a common shortcut,
+    compares columns of different frames and misplaces crossing seams.)"""
+    H, W, C = img.shape
+    out = []
+    for r in range(H):
+        alive = list(range(W))
+        pixels = [alive.pop(int(s[r])) for s in seams_cur]  # the seams' original columns, in order
+        row = [(x, [int(v) for v in img[r, x]]) for x in range(W)]
+        for x in pixels:
+            at = next(i for i, (ox, _) in enumerate(row) if ox == x)
+            a = row[at][1]
+            b = row[at + 1][1] if at + 1 < len(row) else a
+            row.insert(at + 1, (None, [(p + q + 1) >> 1 for p, q in zip(a, b)]))
+        out.append([v for _, v in row])
+    return np.array(out, dtype=np.uint8).reshape(H, W + len(seams_cur), C)
+
+
+def insert_invariants(o, img, k, out, orig, seams_cur):
+    """Width, recovery of the original by deleting the new pixels, the averaging rule, distinct
+    original columns, and that deleting those columns in order reproduces the carve's seams."""
+    H, W, C = img.shape
+    assert out.shape == (H, W + k, C)
+    assert orig.shape == (k, H)
+    for r in range(H):
+        cols = sorted(int(c) for c in orig[:, r])
+        assert len(set(cols)) == k and all(0 <= c < W for c in cols)
+        keep, new, p, mark = [], [], 0, set(cols)
+        for x in range(W):
+            keep.append(p)
+            p += 1
+            if x in mark:
+                new.append((p, x))
+                p += 1
+        assert np.array_equal(out[r, keep], img[r]), "deleting the new pixels must give the original"
+        for pos, x in new:
+            a = img[r, x].astype(int)
+            b = img[r, min(x + 1, W - 1)].astype(int)
+            assert np.array_equal(out[r, pos], ((a + b + 1) >> 1).astype(np.uint8))
+        idx = list(range(W))
+        for j in range(k):
+            s = idx.index(int(orig[j, r]))
+            assert s == int(seams_cur[j, r]), "original columns must map back to the carve's seams"
+            idx.pop(s)
+
+
+def _seams_of(o, img, k):
+    H = img.shape[0]
+    return o.carve(img, img.shape[1] - k)[1] if k else np.zeros((0, H), np.int32)
+
+
+def pin_insert_hand_grids(o):
+    for c in load_golden("insert_grids.json")["cases"]:
+        img = np.array(c["img"], dtype=np.uint8)
+        out, orig = o.insert_seams(img, c["k"])
+        assert np.array_equal(orig, np.array(c["orig"], dtype=np.int32)), c["name"]
+        assert np.array_equal(out, np.array(c["out"], dtype=np.uint8)), c["name"]
+
+
+def pin_insert_sequential_and_invariants(o, n=40, seed=17):
+    rng = np.random.default_rng(seed)
+    for t in range(n):
+        H, W = int(rng.integers(1, 9)), int(rng.integers(2, 13))
+        C = int(rng.choice([1, 3, 4]))
+        alpha = int(rng.choice([2, 4, 256]))
+        img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+        k = int(rng.integers(0, W))
+        out, orig = o.insert_seams(img, k)
+        seams_cur = _seams_of(o, img, k)
+        assert np.array_equal(out, py_insert_sequential(img, seams_cur)), (t, H, W, C, k)
+        insert_invariants(o, img, k, out, orig, seams_cur)
+
+
+def pin_insert_edges(o):
+    rng = np.random.default_rng(5)
+    img = rng.integers(0, 256, size=(6, 9, 3), dtype=np.uint8)
+    out, orig = o.insert_seams(img, 0)
+    assert np.array_equal(out, img) and orig.shape == (0, 6)
+    out, orig = o.insert_seams(img, 8)  # k = W - 1: every pixel but one gets a new neighbour
+    insert_invariants(o, img, 8, out, orig, _seams_of(o, img, 8))
+    const = np.full((5, 7, 3), 77, np.uint8)  # constant image: zero energy, seams at columns 0, 1, 2
+    out, orig = o.insert_seams(const, 3)
+    assert np.array_equal(orig, np.array([[0] * 5, [1] * 5, [2] * 5], np.int32))
+    assert (out == 77).all() and out.shape == (5, 10, 3)
+
+
+ALL_PINS += [pin_insert_hand_grids, pin_insert_sequential_and_invariants, pin_insert_edges]

@@ -16,6 +16,15 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 MUTANTS = {
+    "insert_average_rounds_down": (
+        "o[(size_t)p * C + c] = (uint8_t)((row[(size_t)x * C + c] + row[(size_t)xr * C + c] + 1) >> 1);",
+        "o[(size_t)p * C + c] = (uint8_t)((row[(size_t)x * C + c] + row[(size_t)xr * C + c]) >> 1);"),
+    "insert_left_neighbour": (
+        "int xr = clampi(x + 1, 0, W - 1);",
+        "int xr = clampi(x - 1, 0, W - 1);"),
+    "origins_off_by_one": (
+        "orig[(size_t)j * H + r] = idx[s];",
+        "orig[(size_t)j * H + r] = idx[s < w - 1 ? s + 1 : s];"),
     "parent_tie_rightmost": (
         "if (best < 0 || m[(size_t)(i - 1) * W + p] < m[(size_t)(i - 1) * W + best]) best = p;",
         "if (best < 0 || m[(size_t)(i - 1) * W + p] <= m[(size_t)(i - 1) * W + best]) best = p;"),
