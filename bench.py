@@ -102,9 +102,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["batch", "1080p", "4k"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert"], default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
-                         "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal)")
+                         "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal); "
+                         "insert: 1920x1080 widened by 480 seams")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -287,6 +288,9 @@ def single(args, dev):
     import synth
     from paper_2410_21207_amd import api
 
+    if args.workload == "insert":
+        insert(args, dev)
+        return
     if args.workload == "1080p":
         H, W, seed, tw, th = 1080, 1920, 1, 1440, None
     else:
@@ -337,6 +341,42 @@ def single(args, dev):
                         "kernel": "carve_single_kernel (+ energy pass, transposes)", "model_bytes_per_step": model},
            "latency_ms": round(gpu_s * 1000.0, 3)}
     print(json.dumps(out), flush=True)
+
+
+def insert(args, dev):
+    """Seam insertion: one 1920x1080 image widened by 480 seams (seam search by carving a copy,
+    mapping to original columns, widened image)."""
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    H, W, k = 1080, 1920, 480
+    src = torch.from_numpy(synth.blob_image(H, W, 3, seed=1)).to(dev)
+    out = torch.empty((H, W + k, 3), dtype=torch.uint8, device=dev)
+    ps = H * (k * W - k * (k - 1) // 2)  # the seam search sweeps the same pixels as a carve to W - k
+    _, seams = api.insert_seams(src, k, out=out)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        api.insert_seams(src, k, out=out, record=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        api.insert_seams(src, k, out=out, record=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    gpu_s = e0.elapsed_time(e1) / 1000.0 / args.steps
+    print(json.dumps({"metric": METRIC, "value": round(ps / wall, 1), "unit": "pixel-seams/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1000.0, 3),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                      "data": "synthetic",
+                      "config": {"workload": "seam insertion: one 1920x1080 RGB uint8 blob+noise image (seed 1) "
+                                             "widened by 480 seams", "pixel_seams": ps},
+                      "latency_ms": round(gpu_s * 1000.0, 3)}), flush=True)
 
 
 def cpu_baseline(jobs, imgs_np, gpu_results, seconds):

@@ -140,6 +140,32 @@ sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pi
                    int32_t* seams_out, int64_t* costs_out, const sc_tune* tune, void* ws, size_t ws_bytes,
                    void* stream);
 
+/*
+ * Seam insertion (the "Image Enlargement" subsection of the applications
+ * section): widen img by k columns.  The k minimum seams are found by removal
+ * on a copy, exactly as sc_carve(img -> W - k) removes them; img itself is not
+ * modified.  Mapped to columns of the original image they are k distinct pixels
+ * per row, and inserting the seams one by one in removal order places one new
+ * pixel immediately right of each of them, whose value is the average of its
+ * left and right neighbours, (a + b + 1) >> 1 per channel (a = the seam pixel,
+ * b = the pixel to its right in img; a itself at the last column).
+ *
+ * img:       device, H rows of `pitch` bytes, W*C used (uint8, channels last).
+ * out:       device, H rows of `out_pitch` bytes, (W + k)*C written; must not
+ *            overlap img.
+ * seams_out: nullable device int32 k*H: seam j's original column in row i at
+ *            seams_out[j*H + i], in removal order.
+ * tune:      launch shape of the carve that finds the seams (NULL = default).
+ * ws:        device workspace of sc_insert_workspace_bytes(H, W, C, pitch, k)
+ *            bytes, 256-byte aligned, owned by the caller.
+ * Requires 0 <= k < W and W <= 65536.  Errors: SC_EINVAL (arguments),
+ * SC_ENOMEM (workspace too small), SC_EUNSUPPORTED (W too large), SC_EHIP.
+ * Asynchronous on `stream`.
+ */
+size_t sc_insert_workspace_bytes(int H, int W, int C, int pitch, int k);
+sc_status sc_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, int k, uint8_t* out, int out_pitch,
+                          int32_t* seams_out, const sc_tune* tune, void* ws, size_t ws_bytes, void* stream);
+
 /* One image of a batch (host struct; its pointers are device pointers). */
 typedef struct {
     const uint8_t* src; /* nullable, as in sc_carve */

@@ -47,6 +47,8 @@ SIGNATURES = {
     "sc_variant_count": (I, []),
     "sc_variant_name": (ctypes.c_char_p, [I]),
     "sc_carve": (I, [P, P, I, I, I, I, I, P, P, ctypes.POINTER(sc_tune), P, Z, P]),
+    "sc_insert_workspace_bytes": (Z, [I, I, I, I, I]),
+    "sc_insert_seams": (I, [P, I, I, I, I, I, P, I, P, ctypes.POINTER(sc_tune), P, Z, P]),
     "sc_batch_workspace_bytes": (Z, [ctypes.POINTER(sc_job), I]),
     "sc_batch_prepare": (I, [ctypes.POINTER(sc_job), I, ctypes.POINTER(sc_tune), P, Z,
                              ctypes.POINTER(sc_batch_info)]),

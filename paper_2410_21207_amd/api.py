@@ -13,7 +13,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["energy", "dp_seam", "remove_seam", "transpose", "carve", "carve_hv", "workspace",
+__all__ = ["energy", "dp_seam", "remove_seam", "transpose", "carve", "carve_hv", "insert_seams", "workspace",
            "BatchCarver", "variants", "read_status", "read_times", "read_stages"]
 
 
@@ -139,6 +139,34 @@ def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, rec
     _lib.call("sc_carve", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
               _tune(team, variant, minside), _ptr(ws), ws.numel(), _stream(stream))
     return img[:, : int(target_w)], seams, costs
+
+
+def insert_seams(img: torch.Tensor, k: int, out: torch.Tensor | None = None, record: bool = True,
+                 team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None):
+    """Widen `img` by k seams (img is not modified).
+
+    Returns (out [H, W + k, C], original seam columns int32 [k, H] or None).
+    """
+    H, W, C, pitch = _image(img)
+    k = int(k)
+    if out is None:
+        out = torch.empty((H, W + k, C), dtype=torch.uint8, device=img.device)
+    oH, oW, oC, opitch = _image(out, "out")
+    if (oH, oW, oC) != (H, W + k, C):
+        raise ValueError(f"out must be [{H}, {W + k}, {C}]")
+    if team is None and variant is None:  # the seams come from a carve: use its tuned shape
+        from . import tune
+        variant, team = _tuned(img.device, lambda a: tune.key_single(a, H, W))
+    lib = _lib.load()
+    need = lib.sc_insert_workspace_bytes(H, W, C, pitch, k)
+    if need == 0:
+        raise ValueError(f"bad insertion: H={H}, W={W}, C={C}, k={k}")
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, img.device)
+    seams = torch.empty((k, H), dtype=torch.int32, device=img.device) if record and k > 0 else None
+    _lib.call("sc_insert_seams", _ptr(img), H, W, C, pitch, k, _ptr(out), opitch, _ptr(seams),
+              _tune(team, variant), _ptr(ws), ws.numel(), _stream(stream))
+    return out, seams
 
 
 def carve_hv(img: torch.Tensor, target_w: int, target_h: int, record: bool = True, team=None, variant=None,

@@ -234,6 +234,69 @@ sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pi
     return ok();
 }
 
+namespace {
+// Workspace of sc_insert_seams: the carve's own workspace, a scratch image the carve writes, the
+// seams in removal coordinates and in original columns, and the per-row Fenwick trees.
+struct InsertLayout {
+    size_t carve, scratch, cur, orig, tree, total;
+};
+
+InsertLayout insert_layout(int H, int W, int C, int pitch, int k) {
+    InsertLayout L;
+    size_t off = 0;
+    L.carve = off;
+    off = sc::align_up(off + sc_workspace_bytes(H, W, C), sc::kAlign);
+    L.scratch = off;
+    off = sc::align_up(off + (size_t)H * pitch, sc::kAlign);
+    L.cur = off;
+    off = sc::align_up(off + (size_t)std::max(k, 1) * H * 4, sc::kAlign);
+    L.orig = off;
+    off = sc::align_up(off + (size_t)std::max(k, 1) * H * 4, sc::kAlign);
+    L.tree = off;
+    off = sc::align_up(off + (size_t)(W + 1) * H * 4, sc::kAlign);
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+size_t sc_insert_workspace_bytes(int H, int W, int C, int pitch, int k) {
+    if (H < 1 || W < 1 || C < 1 || C > 4 || pitch < W * C || k < 0 || k >= W) return 0;
+    return insert_layout(H, W, C, pitch, k).total;
+}
+
+sc_status sc_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, int k, uint8_t* out, int out_pitch,
+                          int32_t* seams_out, const sc_tune* tune, void* ws, size_t ws_bytes, void* stream) {
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (!img || !out || !ws) return fail(SC_EINVAL, "null pointer");
+    if (k < 0 || k >= W) return fail(SC_EINVAL, "k=%d not in [0, W=%d)", k, W);
+    if (W > sc::kInsertMaxWidth) return fail(SC_EUNSUPPORTED, "W=%d > %d", W, sc::kInsertMaxWidth);
+    if ((long long)out_pitch < (long long)(W + k) * C)
+        return fail(SC_EINVAL, "out_pitch=%d < (W + k) * C = %lld", out_pitch, (long long)(W + k) * C);
+    const uintptr_t a0 = (uintptr_t)img, a1 = a0 + (size_t)(H - 1) * pitch + (size_t)W * C;
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (size_t)(H - 1) * out_pitch + (size_t)(W + k) * C;
+    if (a0 < b1 && b0 < a1) return fail(SC_EINVAL, "out overlaps img");
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const InsertLayout L = insert_layout(H, W, C, pitch, k);
+    if (ws_bytes < L.total) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    char* base = static_cast<char*>(ws);
+    int32_t* orig = seams_out ? seams_out : reinterpret_cast<int32_t*>(base + L.orig);
+    hipStream_t st = (hipStream_t)stream;
+    if (k > 0) {
+        // the seams: carve a copy (img is the source and stays unmodified), recording each seam
+        s = sc_carve(img, reinterpret_cast<uint8_t*>(base + L.scratch), H, W, C, pitch, W - k,
+                     reinterpret_cast<int32_t*>(base + L.cur), nullptr, tune, base + L.carve,
+                     sc_workspace_bytes(H, W, C), stream);
+        if (s != SC_OK) return s;
+        hipError_t e = sc::launch_seam_origins(reinterpret_cast<const int32_t*>(base + L.cur), k, H, W,
+                                               reinterpret_cast<int32_t*>(base + L.tree), orig, st);
+        if (e != hipSuccess) return hip_fail(e, "seam origins launch");
+    }
+    hipError_t e = sc::launch_insert_seams(img, H, W, C, pitch, k, orig, out, out_pitch, st);
+    if (e != hipSuccess) return hip_fail(e, "insert launch");
+    return ok();
+}
+
 size_t sc_batch_workspace_bytes(const sc_job* jobs, int n) {
     if (!jobs || n < 1) return 0;
     size_t total = ctl_region(n);

@@ -89,5 +89,10 @@ hipError_t launch_prepare_batch(const Img* d_imgs, int n, int max_rows, hipStrea
 hipError_t launch_carve_batch(const Img* d_imgs, const int2* blk, const int2* teams, const int* team_imgs,
                               int nblocks, int variant, hipStream_t st);
 int carve_blocks_per_cu(int variant);  // occupancy of the carve kernel
+hipError_t launch_seam_origins(const int32_t* seams, int k, int H, int W, int32_t* tree, int32_t* orig,
+                               hipStream_t st);
+hipError_t launch_insert_seams(const uint8_t* img, int H, int W, int C, long long pitch, int k, const int32_t* orig,
+                               uint8_t* out, long long out_pitch, hipStream_t st);
+constexpr int kInsertMaxWidth = 65536;
 
 }  // namespace sc

@@ -1135,6 +1135,93 @@ __global__ void unpack_dirs_kernel(Img d, uint8_t* __restrict__ out) {
 }
 
 // ----------------------------------------------------------------------------------------------
+// Seam insertion (image enlargement).
+//
+// Original columns of seams recorded during removal: one thread per row keeps a Fenwick tree over
+// the row's columns still present (1 each) and finds seam j's column as the (s+1)-th present one,
+// then takes it out.  tree: (W + 1) * H int32, entry i of row r at tree[i * H + r] (neighbouring
+// threads touch neighbouring words).
+__global__ void seam_origins_kernel(const int32_t* __restrict__ seams, int k, int H, int W, int32_t* __restrict__ tree,
+                                    int32_t* __restrict__ orig) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= H) return;
+    int32_t* T = tree + r;
+    const size_t st = (size_t)H;
+    for (int i = 1; i <= W; ++i) *gp(T + i * st) = i & -i;
+    int top = 1;
+    while ((top << 1) <= W) top <<= 1;
+    for (int j = 0; j < k; ++j) {
+        int rem = min(max(*gp(seams + (size_t)j * H + r), 0), W - 1 - j) + 1;
+        int pos = 0;  // the largest index whose prefix count is below rem
+        for (int step = top; step > 0; step >>= 1) {
+            const int nx = pos + step;
+            if (nx <= W) {
+                const int v = *gp(T + nx * st);
+                if (v < rem) {
+                    pos = nx;
+                    rem -= v;
+                }
+            }
+        }
+        *gp(orig + (size_t)j * H + r) = pos;  // 0-based column of the (s+1)-th present one
+        for (int i = pos + 1; i <= W; i += i & -i) *gp(T + i * st) -= 1;
+    }
+}
+
+// Widened rows: one workgroup per row marks the seams' original columns in an LDS bitmap, counts
+// the marks per thread chunk, scans the counts, and writes every pixel at its column plus the
+// number of marks left of it, followed by the new pixel ((a + b + 1) >> 1 with the right
+// neighbour; the pixel itself at the last column) where a column is marked.
+constexpr int kInsertThreads = 256;
+constexpr int kInsertMaxW = kInsertMaxWidth;  // the row bitmap lives in LDS
+__global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint8_t* __restrict__ img, int W, int C,
+                                                                    long long pitch, int H, int k,
+                                                                    const int32_t* __restrict__ orig,
+                                                                    uint8_t* __restrict__ out, long long out_pitch) {
+    __shared__ uint32_t bm[kInsertMaxW / 32];
+    __shared__ int part[kInsertThreads];
+    const int r = blockIdx.x, t = threadIdx.x;
+    const int nwords = (W + 31) >> 5;
+    for (int i = t; i < nwords; i += kInsertThreads) bm[i] = 0u;
+    __syncthreads();
+    for (int j = t; j < k; j += kInsertThreads) {
+        const int c = min(max(*gp(orig + (size_t)j * H + r), 0), W - 1);
+        atomicOr(&bm[c >> 5], 1u << (c & 31));
+    }
+    __syncthreads();
+    const int wpt = (nwords + kInsertThreads - 1) / kInsertThreads;  // bitmap words per thread
+    const int w0 = min(t * wpt, nwords), w1 = min(w0 + wpt, nwords);
+    int cnt = 0;
+    for (int i = w0; i < w1; ++i) cnt += __popc(bm[i]);
+    part[t] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int i = 0; i < kInsertThreads; ++i) {
+            const int v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int before = part[t];  // marks left of this thread's first column
+    const uint8_t* row = img + (long long)r * pitch;
+    uint8_t* o = out + (long long)r * out_pitch;
+    for (int c = w0 * 32; c < min(w1 * 32, W); ++c) {
+        const int pos = c + before;
+        for (int ch = 0; ch < C; ++ch) *gp(o + (long long)pos * C + ch) = *gp(row + (long long)c * C + ch);
+        if ((bm[c >> 5] >> (c & 31)) & 1u) {
+            const int cr = c + 1 < W ? c + 1 : c;
+            for (int ch = 0; ch < C; ++ch) {
+                const int a = *gp(row + (long long)c * C + ch), b = *gp(row + (long long)cr * C + ch);
+                *gp(o + (long long)(pos + 1) * C + ch) = (uint8_t)((a + b + 1) >> 1);
+            }
+            ++before;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
 // Variant table and launchers.
 static const Variant kVariants[] = {
     {4, 32, 256, "cpl4_k32_t256"},
@@ -1194,6 +1281,20 @@ hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, int
 
 hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st) {
     hipLaunchKernelGGL(slot_write_kernel, dim3(1), dim3(1), 0, st, table, slot, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_seam_origins(const int32_t* seams, int k, int H, int W, int32_t* tree, int32_t* orig,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(seam_origins_kernel, dim3((H + 63) / 64), dim3(64), 0, st, seams, k, H, W, tree, orig);
+    return hipGetLastError();
+}
+
+hipError_t launch_insert_seams(const uint8_t* img, int H, int W, int C, long long pitch, int k, const int32_t* orig,
+                               uint8_t* out, long long out_pitch, hipStream_t st) {
+    if (W > kInsertMaxW) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(insert_seams_kernel, dim3(H), dim3(kInsertThreads), 0, st, img, W, C, pitch, H, k, orig, out,
+                       out_pitch);
     return hipGetLastError();
 }
 
