@@ -357,6 +357,17 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     std::vector<int> gsz(n, 1);
     if (G > 1)
         for (int i = 0; i < n; ++i) gsz[i] = (int)std::min<double>(G, std::max(1.0, std::ceil(work[i] / per_slot)));
+    // The image with the longest chain of seams x rows sets the batch time; it alone gets twice
+    // the largest team (its removal and band work split over more waves), room permitting.
+    if (G > 1 && n > 1) {
+        int crit = 0;
+        double cbest = -1;
+        for (int i = 0; i < n; ++i) {
+            const double c = (double)(jobs[i].W - jobs[i].target_w) * (jobs[i].H + 64);
+            if (c > cbest) cbest = c, crit = i;
+        }
+        gsz[crit] = std::min(std::min(2 * G, 32), per_xcd);
+    }
     // Wave priorities: an image's latency grows with its row chain, seams x rows; images whose
     // chain is within 2x, 4x, 8x of the longest get priority 3, 2, 1 on their SIMDs.
     std::vector<int> prio(n, 0);
