@@ -38,7 +38,8 @@
  *       removal on a copy; in the original image the recorded seams are k
  *       distinct pixels per row, so inserting the seams one by one in removal
  *       order puts one new pixel immediately right of each recorded pixel.
- *   R16 value of an inserted pixel ("average of the left/right neighbours"):
+ *   R16 value of an inserted pixel (an average of its horizontal neighbours,
+ *       rounding not stated):
  *       (a + b + 1) >> 1 per channel, a = the recorded pixel, b = its right
  *       neighbour in the original image (a itself at the last column).
  */
