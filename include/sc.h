@@ -116,6 +116,11 @@ typedef struct {
 /* Batches: run every image at the same wave priority (by default the images with the longest
  * seams-by-rows chains run at a raised priority on their SIMDs).  Results are identical. */
 #define SC_TUNE_NO_PRIO 2
+/* sc_carve (and the carve inside sc_insert_seams): bits 8..10 of flags name the XCD (0..7) the
+ * team's workgroups run on, so that concurrent carves on different streams can use different
+ * XCDs.  Default 0.  Results are identical. */
+#define SC_TUNE_XCD_SHIFT 8
+#define SC_TUNE_XCD(x) (((x) & 7) << SC_TUNE_XCD_SHIFT)
 
 /* Number of compiled kernel variants and a description of variant v (host memory, static). */
 int sc_variant_count(void);

@@ -23,6 +23,7 @@ class sc_tune(ctypes.Structure):
 
 SC_TUNE_NO_MINSIDE = 1
 SC_TUNE_NO_PRIO = 2
+SC_TUNE_XCD_SHIFT = 8
 
 
 class sc_job(ctypes.Structure):

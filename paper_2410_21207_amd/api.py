@@ -105,11 +105,11 @@ def _tuned(device, key_fn):
     return hit if hit else (None, None)
 
 
-def _tune(team=None, variant=None, minside=True):
-    if team is None and variant is None and minside:
+def _tune(team=None, variant=None, minside=True, xcd=0):
+    if team is None and variant is None and minside and not xcd:
         return None
     return ctypes.byref(_lib.sc_tune(team or 0, -1 if variant is None else variant,
-                                     0 if minside else _lib.SC_TUNE_NO_MINSIDE))
+                                     (0 if minside else _lib.SC_TUNE_NO_MINSIDE) | ((xcd & 7) << _lib.SC_TUNE_XCD_SHIFT)))
 
 
 def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,

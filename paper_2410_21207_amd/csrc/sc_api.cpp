@@ -179,7 +179,7 @@ sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t
                          sc::variant(v).kr, 1, 1);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = sc::launch_prepare_from_i32(d, energy, st);
-    if (e == hipSuccess) e = sc::launch_carve_single(d, v, 1, st);
+    if (e == hipSuccess) e = sc::launch_carve_single(d, v, 1, 0, st);
     if (e == hipSuccess && dirs_out) e = sc::launch_unpack_dirs(d, dirs_out, st);
     if (e != hipSuccess) return hip_fail(e, "dp launch");
     return ok();
@@ -229,7 +229,8 @@ sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pi
     if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) d.minside = 0;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = sc::launch_prepare_single(d, st);
-    if (e == hipSuccess && target_w < W) e = sc::launch_carve_single(d, v, G, st);
+    const int xcd = tune ? (tune->flags >> SC_TUNE_XCD_SHIFT) & 7 : 0;
+    if (e == hipSuccess && target_w < W) e = sc::launch_carve_single(d, v, G, xcd, st);
     if (e != hipSuccess) return hip_fail(e, "carve launch");
     return ok();
 }

@@ -1070,12 +1070,12 @@ struct Carver {
 };
 
 template <int CPL, int KR, int NT>
-__global__ __launch_bounds__(NT, 4) void carve_single_kernel(Img d) {
+__global__ __launch_bounds__(NT, 4) void carve_single_kernel(Img d, int xcd) {
     using CV = Carver<CPL, KR, NT>;
     __shared__ typename CV::Smem sm;
-    // Team members are blocks 0, 8, 16, ...: workgroups are dispatched to the 8 XCDs round-robin
-    // by block index, so they share one XCD's L2; the other blocks exit at once.
-    if (blockIdx.x & 7) return;
+    // Team members are blocks xcd, xcd + 8, xcd + 16, ...: workgroups are dispatched to the 8 XCDs
+    // round-robin by block index, so they share XCD `xcd`'s L2; the other blocks exit at once.
+    if ((int)(blockIdx.x & 7) != xcd) return;
     CV::carve_image(d, blockIdx.x >> 3, d.G, sm, 0);
 }
 
@@ -1243,10 +1243,10 @@ int team_variant() { return 7; }
     X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) X(6, 4, 48, 256) \
     X(7, 4, 56, 512) X(8, 4, 56, 256)
 
-hipError_t launch_carve_single(const Img& d, int v, int G, hipStream_t st) {
+hipError_t launch_carve_single(const Img& d, int v, int G, int xcd, hipStream_t st) {
     switch (v) {
 #define X(id, c, k, t) \
-    case id: hipLaunchKernelGGL((carve_single_kernel<c, k, t>), dim3(8 * G), dim3(t), 0, st, d); break;
+    case id: hipLaunchKernelGGL((carve_single_kernel<c, k, t>), dim3(8 * G), dim3(t), 0, st, d, xcd & 7); break;
         SC_VARIANTS(X)
 #undef X
         default: return hipErrorInvalidValue;

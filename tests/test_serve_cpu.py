@@ -159,3 +159,4 @@ def test_open_loop_run_with_virtual_time():
     assert st["done"] == 10 and st["errors"] == 0
     for t, r in zip(srv.tickets, arrivals):
         assert np.array_equal(t.result[0], oracle.carve(r.img, r.target_w)[0])
+
