@@ -232,11 +232,18 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
  *                  (device int32; -1 = device error, -2 = empty slot).  A slot is done when
  *                  progress equals W - target_w.  Calls that share a table must be ordered on
  *                  one stream.
+ *   sc_slots_step_timed  the same with a time budget: each image's workgroup stops after the
+ *                  first seam that ends budget_us microseconds (device wall clock) or more after
+ *                  it started in this launch, or after max_seams seams; budget_us = 0 is
+ *                  sc_slots_step.  A step's workgroups then stay busy for about the same time
+ *                  instead of waiting for the one with the most work.
  */
 size_t sc_slot_table_bytes(int n_slots);
 sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int slot, void* stream);
 sc_status sc_slot_clear(void* table, int slot, void* stream);
 sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream);
+sc_status sc_slots_step_timed(const void* table, int n_slots, int max_seams, long long budget_us, int32_t* progress,
+                              void* stream);
 
 /*
  * Device-side status of the images of a workspace (synchronous: waits for the

@@ -65,6 +65,7 @@ SIGNATURES = {
     "sc_slot_start": (I, [ctypes.POINTER(sc_job), P, Z, P, I, P]),
     "sc_slot_clear": (I, [P, I, P]),
     "sc_slots_step": (I, [P, I, I, P, P]),
+    "sc_slots_step_timed": (I, [P, I, I, ctypes.c_longlong, P, P]),
 }
 
 _lib = None

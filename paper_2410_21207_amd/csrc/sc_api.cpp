@@ -631,9 +631,16 @@ extern "C" sc_status sc_slot_clear(void* table, int slot, void* stream) {
 }
 
 extern "C" sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream) {
-    if (!table || n_slots < 1 || max_seams < 1) return fail(SC_EINVAL, "bad slot step arguments");
+    return sc_slots_step_timed(table, n_slots, max_seams, 0, progress, stream);
+}
+
+extern "C" sc_status sc_slots_step_timed(const void* table, int n_slots, int max_seams, long long budget_us,
+                                         int32_t* progress, void* stream) {
+    if (!table || n_slots < 1 || max_seams < 1 || budget_us < 0) return fail(SC_EINVAL, "bad slot step arguments");
+    // the device wall clock runs at 100 MHz: 100 ticks per microsecond
     hipError_t e = sc::launch_carve_steps(static_cast<const sc::Img*>(table), n_slots, sc::default_variant(),
-                                          max_seams, progress, (hipStream_t)stream);
+                                          max_seams, (unsigned long long)budget_us * 100ull, progress,
+                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "slot step");
     return ok();
 }

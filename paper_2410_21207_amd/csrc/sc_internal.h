@@ -78,7 +78,8 @@ hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long 
 hipError_t launch_prepare_single(const Img& d, hipStream_t st);          // energy plane (+copy, ctl zero)
 hipError_t launch_prepare_from_i32(const Img& d, const int32_t* energy, hipStream_t st);
 hipError_t launch_carve_single(const Img& d, int variant, int G, int xcd, hipStream_t st);
-hipError_t launch_carve_steps(const Img* table, int n, int variant, int max_seams, int* progress, hipStream_t st);
+hipError_t launch_carve_steps(const Img* table, int n, int variant, int max_seams, unsigned long long budget_ticks,
+                              int* progress, hipStream_t st);
 hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st);
 hipError_t launch_unpack_dirs(const Img& d, uint8_t* out, hipStream_t st);
 hipError_t launch_remove_seam(uint8_t* img, int H, int W, int C, long long pitch, const int32_t* seam,

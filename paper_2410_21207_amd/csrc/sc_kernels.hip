@@ -559,6 +559,7 @@ struct Carver {
         uint32_t win[NW][KR * WD];         // backtrack windows of the direction map
         int chain;                         // jend[p] is final for every p >= chain
         int flag;
+        int stop;                          // step mode: the time budget is spent
     };
 
     struct EV {
@@ -824,10 +825,12 @@ struct Carver {
         return true;
     }
 
-    // Seams k_begin .. k_end-1 of one image (the image has W - k_begin columns on entry).
+    // Seams k_begin .. k_end-1 of one image (the image has W - k_begin columns on entry).  With a
+    // deadline (device wall clock; one workgroup only) it stops after the first seam that ends
+    // past it.  Returns the number of seams removed in total (k_begin + the seams of this call).
     template <bool TEAM>
-    static __device__ __forceinline__ void carve_seams(const Img& d, int rank, int G, Smem& sm, int k_begin, int k_end,
-                                       unsigned& epoch) {
+    static __device__ __forceinline__ int carve_seams(const Img& d, int rank, int G, Smem& sm, int k_begin, int k_end,
+                                                      unsigned& epoch, unsigned long long deadline) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         // waves are numbered across the team first, so a phase's strips land on different compute
         // units (one DP wave per SIMD) before any workgroup takes a second one
@@ -861,7 +864,7 @@ struct Carver {
                     const bool ok = (base < 0 || base + WIN > w)
                                         ? dp_item<true, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P, rovc)
                                         : dp_item<false, TEAM>(d, sm, w, p, t, lane, ring, preloaded, nx, k * P, rovc);
-                    if (!ok) return;
+                    if (!ok) return k;
                     preloaded = nx.valid && ((min(H, p * KR + KR) - p * KR) % PF == 0);
                 }
                 // one workgroup exchanges phase ends through LDS behind a barrier; a team's waves
@@ -870,7 +873,7 @@ struct Carver {
             }
             // the directions, ancestor offsets and argmin of every phase are complete past here
             if constexpr (TEAM) {
-                if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+                if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
             }
             if (timer) tm1 = wall_clock64();
             const unsigned long long key = __hip_atomic_load(d.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -988,7 +991,7 @@ struct Carver {
                     }
                 }
             }
-            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
             if (timer) tm2 = wall_clock64();
             if (d.mode) break;
             if (rank == 0 && threadIdx.x == 0)
@@ -1009,12 +1012,19 @@ struct Carver {
                     if (s < w2) *gp(er + s) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s);
                 }
             }
-            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return;
+            if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
             if (timer) {
                 const unsigned long long tm3 = wall_clock64();
                 ctl->t_stage[0] += tm1 - tm0;
                 ctl->t_stage[1] += tm2 - tm1;
                 ctl->t_stage[2] += tm3 - tm2;
+            }
+            if (deadline && G == 1 && k + 1 < k_end) {  // one decision for the whole workgroup
+                if (threadIdx.x == 0) sm.stop = wall_clock64() >= deadline;
+                __syncthreads();
+                const int stop = sm.stop;
+                __syncthreads();
+                if (stop) k_end = k + 1;
             }
         }
         // ---- after the last seam, the carved rows go from wk (each from its start offset) to img
@@ -1032,10 +1042,12 @@ struct Carver {
             }
             team_sync<TEAM>(d, epoch, G, &sm.flag);
         }
+        return k_end;
     }
 
     // Carve one image, or (max_seams > 0) continue it by at most max_seams seams.
-    static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams) {
+    static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams,
+                                                       unsigned long long deadline = 0) {
         Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
         set_prio(d.prio);
         const int nseams = d.mode ? 1 : d.W - d.target_w;
@@ -1044,6 +1056,7 @@ struct Carver {
         if (k0 >= k1) return;
         if (rank == 0 && threadIdx.x == 0 && k0 == 0) ctl->t_begin = wall_clock64();
         unsigned epoch = 0;
+        int kd = k0;  // seams removed in total when this call ends
         const bool team = G > 1 || d.W > kLdsExchangeMaxW;
         if (team) {
             // every member records its XCD; a team spread over several XCDs would not see each
@@ -1057,14 +1070,14 @@ struct Carver {
                     __hip_atomic_fetch_or(d.status, kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return;
             }
-            carve_seams<true>(d, rank, G, sm, k0, k1, epoch);
+            kd = carve_seams<true>(d, rank, G, sm, k0, k1, epoch, deadline);
         } else {
-            carve_seams<false>(d, rank, G, sm, k0, k1, epoch);
+            kd = carve_seams<false>(d, rank, G, sm, k0, k1, epoch, deadline);
         }
         __syncthreads();
         if (rank == 0 && threadIdx.x == 0) {
-            ctl->done = (unsigned)k1;
-            if (k1 == nseams) ctl->t_end = wall_clock64();
+            ctl->done = (unsigned)kd;
+            if (kd == nseams) ctl->t_end = wall_clock64();
         }
     }
 };
@@ -1103,6 +1116,7 @@ __global__ __launch_bounds__(NT, 4) void carve_batch_kernel(const Img* __restric
 // written by slot_start_kernel, so each block reads its descriptor with scalar loads.
 template <int CPL, int KR, int NT>
 __global__ __launch_bounds__(NT, 4) void carve_steps_kernel(const Img* __restrict__ table, int n, int max_seams,
+                                                            unsigned long long budget_ticks,
                                                             int* __restrict__ progress) {
     using CV = Carver<CPL, KR, NT>;
     __shared__ typename CV::Smem sm;
@@ -1113,7 +1127,9 @@ __global__ __launch_bounds__(NT, 4) void carve_steps_kernel(const Img* __restric
         if (threadIdx.x == 0 && progress) progress[b] = -2;
         return;
     }
-    CV::carve_image(d, 0, 1, sm, max_seams);
+    // a time budget (device wall clock ticks) ends the workgroup's share after the seam that
+    // crosses it, so a step's workgroups stay busy for about the same time
+    CV::carve_image(d, 0, 1, sm, max_seams, budget_ticks ? wall_clock64() + budget_ticks : 0ull);
     __syncthreads();
     if (threadIdx.x == 0 && progress) {
         const Ctl* ctl = reinterpret_cast<const Ctl*>(d.amin);
@@ -1266,11 +1282,13 @@ hipError_t launch_carve_batch(const Img* imgs, const int2* blk, const int2* team
     return hipGetLastError();
 }
 
-hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, int* progress, hipStream_t st) {
+hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, unsigned long long budget_ticks,
+                              int* progress, hipStream_t st) {
     switch (v) {
 #define X(id, c, k, t)                                                                                        \
     case id:                                                                                                  \
-        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, table, n, max_seams, progress); \
+        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, table, n, max_seams, budget_ticks, \
+                           progress);                                                                              \
         break;
         SC_VARIANTS(X)
 #undef X

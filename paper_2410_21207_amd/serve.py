@@ -3,14 +3,16 @@
 Requests of different sizes arrive over time.  The server admits them in arrival order as soon
 as a slot and enough of the HBM budget are free, keeps every admitted image and its carve state
 on the device between seams, and advances ALL admitted images together: one step is one launch
-of the step kernel (``sc_slots_step``) that removes up to ``seams_per_step`` seams from every
-active slot, one workgroup per image.  A request that arrives while others are mid-carve joins
-at the next step; its work overlaps theirs on the device.  Latency is arrival to completion.
+of the step kernel (``sc_slots_step_timed``), one workgroup per image, in which every active
+image removes seams until the step's time budget is spent (or ``seams_per_step`` seams): small
+requests finish within a step and no workgroup waits for the largest one.  A request that
+arrives while others are mid-carve joins at the next step; its work overlaps theirs on the
+device.  Latency is arrival to completion.
 
 The executor is an interface: ``GPUExecutor`` drives the C ABI; tests drive the same scheduler
 with a fake executor on the CPU.
 
-    python -m paper_2410_21207_amd.serve [--rate 300] [--duration 60] [--budget-gb 64]
+    python -m paper_2410_21207_amd.serve [--rate 300] [--duration 60] [--budget-gb 64] [--step-us 20000]
 """
 from __future__ import annotations
 
@@ -73,11 +75,12 @@ class Server:
     """FIFO admission by HBM budget and free slots; continuous batching of the carve steps."""
 
     def __init__(self, executor, budget_bytes: int = 64 << 30, max_slots: int = 256, seams_per_step: int = 16,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, step_budget_us: int = 0):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.seams_per_step = int(seams_per_step)
+        self.step_budget_us = int(step_budget_us)  # > 0: steps end on time, seams_per_step is a cap
         self.clock = clock
         self.queue: deque[Ticket] = deque()
         self.active: dict[int, Ticket] = {}
@@ -134,7 +137,8 @@ class Server:
         if not self.active:
             return []
         n = max(self.active) + 1
-        progress = self.ex.advance(n, self.seams_per_step)
+        progress = (self.ex.advance(n, self.seams_per_step, self.step_budget_us) if self.step_budget_us
+                    else self.ex.advance(n, self.seams_per_step))
         self.steps += 1
         now = self.clock()
         finished = []
@@ -281,9 +285,9 @@ class GPUExecutor:
         _lib.call("sc_slot_start", ctypes.byref(job), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                   ctypes.c_void_p(self.table.data_ptr()), slot, ctypes.c_void_p(self.stream.cuda_stream))
 
-    def advance(self, n, max_seams):
-        self._lib.call("sc_slots_step", ctypes.c_void_p(self.table.data_ptr()), n, max_seams,
-                  ctypes.c_void_p(self.progress.data_ptr()), ctypes.c_void_p(self.stream.cuda_stream))
+    def advance(self, n, max_seams, budget_us: int = 0):
+        self._lib.call("sc_slots_step_timed", ctypes.c_void_p(self.table.data_ptr()), n, max_seams, int(budget_us),
+                       ctypes.c_void_p(self.progress.data_ptr()), ctypes.c_void_p(self.stream.cuda_stream))
         with self.torch.cuda.stream(self.stream):  # ordered after the step on the same stream
             self.progress_host[:n].copy_(self.progress[:n], non_blocking=True)
         self.stream.synchronize()
@@ -314,7 +318,9 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=512)
-    ap.add_argument("--seams-per-step", type=int, default=16)
+    ap.add_argument("--seams-per-step", type=int, default=1 << 20, help="cap on the seams a slot removes per step")
+    ap.add_argument("--step-us", type=int, default=20000,
+                    help="time budget of a step in microseconds (0: every slot removes seams-per-step seams)")
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--big-work", type=float, default=0,
                     help="requests of at least this many pixel-seams are carved whole by a team on a side stream "
@@ -334,14 +340,14 @@ def main():
 
     srv = Server(GPUExecutor(args.slots, dev, big_work=args.big_work or None), budget_bytes=int(args.budget_gb * 1e9),
                  max_slots=args.slots,
-                 seams_per_step=args.seams_per_step)
+                 seams_per_step=args.seams_per_step, step_budget_us=args.step_us)
     st = srv.run(reqs, payload, progress=lambda m: print(m, file=sys.stderr, flush=True))
     offered = sum(r.h * ((r.w - r.target_w) * r.w - (r.w - r.target_w) * (r.w - r.target_w - 1) // 2)
                   for r in reqs) / args.duration
     st.update({"workload": f"Poisson {args.rate}/s for {args.duration}s, sides log-uniform [128,4096], "
                            "target 50-90% of width, 64 GB budget",
                "offered_pixel_seams_per_s": round(offered, 1), "seams_per_step": args.seams_per_step,
-               "big_work": args.big_work,
+               "big_work": args.big_work, "step_us": args.step_us,
                "slots": args.slots})
     print(json.dumps(st), flush=True)
 

@@ -24,12 +24,13 @@ def _requests(n, seed):
     return out
 
 
-@pytest.mark.parametrize("seams_per_step", [1, 7])
-def test_served_in_mix_equals_alone(seams_per_step):
-    reqs = _requests(24, seed=seams_per_step)
-    log("serve mix", seams_per_step)
+@pytest.mark.parametrize("seams_per_step,step_us", [(1, 0), (7, 0), (1 << 20, 300)])
+def test_served_in_mix_equals_alone(seams_per_step, step_us):
+    reqs = _requests(24, seed=seams_per_step % 1000 + step_us)
+    log("serve mix", seams_per_step, step_us)
     budget = 6 * max(2 * img.nbytes for img, _ in reqs) + 8 * (1 << 20)
-    srv = Server(GPUExecutor(16), budget_bytes=budget, max_slots=16, seams_per_step=seams_per_step)
+    srv = Server(GPUExecutor(16), budget_bytes=budget, max_slots=16, seams_per_step=seams_per_step,
+                 step_budget_us=step_us)
     ts = [srv.submit(img.shape[0], img.shape[1], 3, tw, dev(img)) for img, tw in reqs]
     while not srv.idle():
         srv.step()
