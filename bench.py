@@ -102,10 +102,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep"], default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
                          "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal); "
-                         "insert: 1920x1080 widened by 480 seams")
+                         "insert: 1920x1080 widened by 480 seams; sweep: the paper's size sweep of square "
+                         "images, GPU DP against the CPU oracle's DP, greedy and brute force")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -291,6 +292,9 @@ def single(args, dev):
     if args.workload == "insert":
         insert(args, dev)
         return
+    if args.workload == "sweep":
+        sweep(args, dev)
+        return
     if args.workload == "1080p":
         H, W, seed, tw, th = 1080, 1920, 1, 1440, None
     else:
@@ -377,6 +381,117 @@ def insert(args, dev):
                       "config": {"workload": "seam insertion: one 1920x1080 RGB uint8 blob+noise image (seed 1) "
                                              "widened by 480 seams", "pixel_seams": ps},
                       "latency_ms": round(gpu_s * 1000.0, 3)}), flush=True)
+
+
+def _slope(ns, ts):
+    """Least-squares slope of log(time) against log(n)."""
+    x, y = np.log(np.asarray(ns, float)), np.log(np.asarray(ts, float))
+    return float(np.polyfit(x, y, 1)[0])
+
+
+def sweep(args, dev):
+    """The paper's runtime experiment re-run on MI355X: one square blob image at 180, 360, 480, 720
+    and 1080 px (nearest-neighbour versions of the 1080 px image), carved to half its width
+    (s = 0.5) by the GPU DP path; the CPU legs time the oracle's DP carve and a greedy carve on one
+    host core, and the oracle's brute force on 2..12 px images.  T = one seam, C = the carve."""
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    base = synth.blob_image(1080, 1080, 3, seed=6)
+    rows = []
+    for n in (180, 360, 480, 720, 1080):
+        img = synth.resized(base, n)
+        src = torch.from_numpy(img).to(dev)
+        dst = torch.empty_like(src)
+        e = api.energy(src)
+        api.dp_seam(e)
+        api.carve(dst, n // 2, src=src)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            api.dp_seam(e)
+        torch.cuda.synchronize()
+        t_gpu = (time.perf_counter() - t) / args.steps
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, seams, _ = api.carve(dst, n // 2, src=src)
+        torch.cuda.synchronize()
+        c_gpu = (time.perf_counter() - t) / args.steps
+        rows.append({"n": n, "gpu_T_ms": round(t_gpu * 1e3, 3), "gpu_C_ms": round(c_gpu * 1e3, 3),
+                     "_img": img, "_seams": seams.cpu().numpy()})
+    out = {"metric": METRIC, "value": None, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "higher_is_better": False, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "size sweep: square blob image (seed 6) at 180-1080 px, half the width removed"}}
+    if not args.no_cpu:
+        cpu_baseline_sweep(rows)
+    for r in rows:
+        r.pop("_img"), r.pop("_seams")
+    out["sweep"] = rows
+    ns = [r["n"] for r in rows]
+    out["slopes_loglog"] = {"gpu_T": round(_slope(ns, [r["gpu_T_ms"] for r in rows]), 2),
+                            "gpu_C": round(_slope(ns, [r["gpu_C_ms"] for r in rows]), 2)}
+    if not args.no_cpu:
+        for key in ("dp_T_ms", "dp_C_ms", "greedy_T_ms", "greedy_C_ms"):
+            out["slopes_loglog"][key[:-3]] = round(_slope(ns, [r[key] for r in rows]), 2)
+        out["brute_force"] = cpu_brute_sweep()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_sweep(rows):
+    """The oracle on one host core at every size of the sweep: its DP seam (T) and carve (C), and a
+    greedy carve built from its greedy seam; the GPU seams must equal the oracle's."""
+    import oracle
+
+    oracle.default()
+    for r in rows:
+        img, n = r["_img"], r["n"]
+        e = oracle.energy(img)
+        t = time.perf_counter()
+        oracle.dp_seam(e)
+        r["dp_T_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+        t = time.perf_counter()
+        _, seams, _ = oracle.carve(img, n // 2)
+        r["dp_C_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+        r["seams_match_gpu"] = bool(np.array_equal(seams, r["_seams"]))
+        t = time.perf_counter()
+        oracle.greedy_seam(e)
+        r["greedy_T_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+        cur = img.copy()
+        t = time.perf_counter()
+        for _ in range(n // 2):
+            s, _ = oracle.greedy_seam(oracle.energy(cur))
+            cur = oracle.remove_seam(cur, s)
+        r["greedy_C_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+
+
+def cpu_brute_sweep():
+    """Brute force (the oracle's exhaustive seam search) at the paper's sizes 2..12 px."""
+    import oracle
+
+    import synth
+    out = []
+    base = synth.blob_image(1080, 1080, 3, seed=6)
+    for n in (2, 5, 7, 10, 12):
+        img = synth.resized(base, n)
+        e = oracle.energy(img)
+        t = time.perf_counter()
+        oracle.brute_seam(e)
+        t_seam = time.perf_counter() - t
+        cur = img.copy()
+        t = time.perf_counter()
+        for _ in range(max(1, n // 2)):
+            s, _ = oracle.brute_seam(oracle.energy(cur))
+            cur = oracle.remove_seam(cur, s)
+        out.append({"n": n, "T_ms": round(t_seam * 1e3, 4), "C_ms": round((time.perf_counter() - t) * 1e3, 4)})
+    ns = np.array([o["n"] for o in out], float)
+    # T(n, n) ~ n 3^n: the slope of log(T / n) against n estimates log 3 (fitted on 10 and 12 px:
+    # below that a seam takes microseconds and call overhead dominates)
+    big = ns >= 10
+    tt = np.array([o["T_ms"] for o in out])[big]
+    out_fit = float(np.polyfit(ns[big], np.log(tt / ns[big]), 1)[0])
+    return {"sizes": out, "fit_log_base_of_T_over_n_10_12": round(out_fit, 3), "log_3": round(float(np.log(3)), 3)}
 
 
 def cpu_baseline(jobs, imgs_np, gpu_results, seconds):

@@ -148,3 +148,13 @@ def serving_requests(rate: float = 300.0, duration: float = 60.0, seed: int = 4,
 def canvas_crop(canvases, req: Request) -> np.ndarray:
     """Pixels of a request: a crop of one of the pre-generated canvases."""
     return np.ascontiguousarray(canvases[req.canvas][req.y0:req.y0 + req.h, req.x0:req.x0 + req.w])
+
+
+def resized(img: np.ndarray, n: int, m: int | None = None) -> np.ndarray:
+    """Nearest-neighbour resampling of an image to n rows and m (default n) columns: the
+    different-sized versions of one image used by the size sweep."""
+    m = n if m is None else m
+    H, W = img.shape[:2]
+    ys = (np.arange(n) * H) // n
+    xs = (np.arange(m) * W) // m
+    return np.ascontiguousarray(img[ys][:, xs])
