@@ -100,3 +100,33 @@ def test_batch_validation(lib):
     assert b"job 1" in lib.sc_last_error()
     assert lib.sc_batch_workspace_bytes(jobs, 2) > 0
     assert lib.sc_batch_launch(ctypes.byref(info), FAKE, None) == _lib.SC_EINVAL  # nothing prepared
+
+
+def test_insert_validation(lib):
+    assert lib.sc_insert_workspace_bytes(10, 10, 3, 30, 10) == 0  # k must be < W
+    assert lib.sc_insert_workspace_bytes(10, 10, 3, 20, 2) == 0   # pitch < W * C
+    assert lib.sc_insert_workspace_bytes(10, 10, 3, 30, -1) == 0
+    a = lib.sc_insert_workspace_bytes(1080, 1920, 3, 5760, 480)
+    assert a > lib.sc_workspace_bytes(1080, 1920, 3) + 1080 * 5760 and a % 256 == 0
+    big = ctypes.c_void_p(1 << 40)
+    # k out of range, short output pitch, overlapping buffers, small workspace: all rejected up front
+    assert lib.sc_insert_seams(FAKE, 4, 8, 3, 24, 8, big, 48, None, None, FAKE, 1 << 20, None) == _lib.SC_EINVAL
+    assert lib.sc_insert_seams(FAKE, 4, 8, 3, 24, 2, big, 29, None, None, FAKE, 1 << 20, None) == _lib.SC_EINVAL
+    assert lib.sc_insert_seams(FAKE, 4, 8, 3, 24, 2, ctypes.c_void_p(0x1010), 30, None, None, big, 1 << 20,
+                               None) == _lib.SC_EINVAL
+    assert lib.sc_insert_seams(FAKE, 4, 8, 3, 24, 2, big, 30, None, None, ctypes.c_void_p(1 << 41), 64,
+                               None) == _lib.SC_ENOMEM
+
+
+def test_slot_step_validation(lib):
+    assert lib.sc_slots_step(None, 4, 16, None, None) == _lib.SC_EINVAL
+    assert lib.sc_slots_step_timed(FAKE, 4, 16, -1, None, None) == _lib.SC_EINVAL
+    assert lib.sc_slots_step_timed(FAKE, 0, 16, 100, None, None) == _lib.SC_EINVAL
+
+
+def test_tune_flag_bits_do_not_overlap():
+    flags = [_lib.SC_TUNE_NO_MINSIDE, _lib.SC_TUNE_NO_PRIO] + [x << _lib.SC_TUNE_XCD_SHIFT for x in (1, 2, 4)]
+    acc = 0
+    for f in flags:
+        assert acc & f == 0
+        acc |= f
