@@ -75,6 +75,8 @@ class Oracle:
             "sco_insert_seams": [P, I, I, I, I, I, P, I, P],
             "sco_greedy_seam": [P, I, I, P, P],
             "sco_brute_seam": [P, I, I, P, P],
+            "sco_forward_dp": [P, I, I, I, I, P, P, P, P],
+            "sco_carve_forward": [P, I, I, I, I, I, P, P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -165,6 +167,33 @@ class Oracle:
         _check(self.lib.sco_insert_seams(_p(img), H, W, C, W * C, k, _p(out), (W + k) * C, _p(orig)), "insert_seams")
         return out, orig[:k]
 
+    def forward_seam(self, img, full: bool = False):
+        """Minimum forward-energy seam of a uint8 [H, W, C] image.
+
+        Returns (seam int32 [H], cost int) or, with ``full``, also the cumulative
+        table M (int64 [H, W]) and the direction map D (uint8 [H, W], 0/1/2).
+        """
+        img = _img(img)
+        H, W, C = img.shape
+        seam = np.empty(H, np.int32)
+        cost = np.zeros(1, np.int64)
+        M = np.empty((H, W), np.int64) if full else None
+        D = np.empty((H, W), np.uint8) if full else None
+        _check(self.lib.sco_forward_dp(_p(img), H, W, C, W * C, _p(M), _p(D), _p(seam), _p(cost)), "forward_dp")
+        if full:
+            return seam, int(cost[0]), M, D
+        return seam, int(cost[0])
+
+    def carve_forward(self, img, target_w: int):
+        """Forward-energy carve -> (image [H,target_w,C], seams [k,H], costs [k])."""
+        img = _img(img).copy()
+        H, W, C = img.shape
+        k = W - target_w
+        seams = np.empty((max(k, 0), H), np.int32)
+        costs = np.empty(max(k, 0), np.int64)
+        _check(self.lib.sco_carve_forward(_p(img), H, W, C, W * C, target_w, _p(seams), _p(costs)), "carve_forward")
+        return np.ascontiguousarray(img[:, :target_w]), seams, costs
+
     def greedy_seam(self, e):
         """Alg. 2 greedy seam of an int32 [H, W] energy map -> (seam, cost)."""
         e = np.ascontiguousarray(np.asarray(e, dtype=np.int32))
@@ -229,3 +258,11 @@ def greedy_seam(e):
 
 def brute_seam(e):
     return default().brute_seam(e)
+
+
+def forward_seam(img, full: bool = False):
+    return default().forward_seam(img, full)
+
+
+def carve_forward(img, target_w: int):
+    return default().carve_forward(img, target_w)

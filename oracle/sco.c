@@ -42,6 +42,26 @@
  *       rounding not stated):
  *       (a + b + 1) >> 1 per channel, a = the recorded pixel, b = its right
  *       neighbour in the original image (a itself at the last column).
+ *   R17 forward energy (sec. "Forward Energy Calculation" names the idea, the
+ *       cost of the pixel pairs that become neighbours when the seam pixel
+ *       goes, and gives no formula): the standard definition of Rubinstein,
+ *       Shamir and Avidan (SIGGRAPH 2008) with its optional per-pixel term
+ *       set to zero.  With D(p,q) = sum over channels of |I(p)-I(q)|:
+ *         CU(i,j) = D((i,j-1),(i,j+1))               (the new horizontal pair)
+ *         CL(i,j) = CU(i,j) + D((i-1,j),(i,j-1))      (parent (i-1,j-1))
+ *         CR(i,j) = CU(i,j) + D((i-1,j),(i,j+1))      (parent (i-1,j+1))
+ *         M(i,j)  = min(M(i-1,j-1)+CL, M(i-1,j)+CU, M(i-1,j+1)+CR)
+ *   R18 forward energy at the border: a neighbour index outside the row is
+ *       clamped to it, as R2 does for e1, so removing a border pixel costs its
+ *       difference to the pixel that becomes the border,
+ *       CU(i,0) = D((i,0),(i,1)) and CU(i,w-1) = D((i,w-2),(i,w-1)) (0 when
+ *       w == 1); parents outside the row are excluded as in R4.  (Charging
+ *       nothing at the border would make the border column a zero-cost seam
+ *       of every image.)
+ *   R19 first row of the forward table: M(0,j) = CU(0,j) (only the new
+ *       horizontal pair).  Ties, backtrack, removal and the carve loop are
+ *       R5-R9 unchanged; the costs are recomputed from the current pixels for
+ *       every seam.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -250,6 +270,90 @@ int sco_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, int k, 
     free(seams);
     free(orig);
     free(mark);
+    return rc;
+}
+
+/*
+ * D(p,q) of R17: the sum over channels of the absolute pixel difference.
+ */
+static int64_t pix_diff(const uint8_t* img, int pitch, int C, int y0, int x0, int y1, int x1) {
+    int64_t s = 0;
+    for (int c = 0; c < C; ++c)
+        s += absi((int)img[(size_t)y0 * pitch + (size_t)x0 * C + c] - (int)img[(size_t)y1 * pitch + (size_t)x1 * C + c]);
+    return s;
+}
+
+/*
+ * Forward-energy seam (sec. "Forward Energy Calculation", readings R17-R19)
+ * of the H x W x C image img: the DP of Alg. 3 with the per-pixel energy
+ * replaced by the cost of the pairs each removal creates.
+ * M: nullable, H*W int64 (the cumulative table); D: nullable, H*W uint8,
+ * parent direction best-j+1 (row 0: 1).  seam/cost as for sco_dp.
+ */
+int sco_forward_dp(const uint8_t* img, int H, int W, int C, int pitch, int64_t* M, uint8_t* D, int32_t* seam,
+                   int64_t* cost) {
+    if (!img || !seam || !cost || H < 1 || W < 1 || C < 1 || pitch < W * C) return SCO_EINVAL;
+    int64_t* m = M ? M : (int64_t*)malloc(sizeof(int64_t) * (size_t)H * W);
+    uint8_t* d = D ? D : (uint8_t*)malloc((size_t)H * W);
+    if (!m || !d) {
+        if (!M) free(m);
+        if (!D) free(d);
+        return SCO_ENOMEM;
+    }
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            /* R17/R18: the new horizontal pair, neighbours clamped to the row */
+            int64_t cu = pix_diff(img, pitch, C, i, clampi(j - 1, 0, W - 1), i, clampi(j + 1, 0, W - 1));
+            if (i == 0) {                                /* R19 */
+                m[j] = cu;
+                d[j] = 1;
+                continue;
+            }
+            int best = -1;
+            int64_t bestv = 0;
+            for (int p = j - 1; p <= j + 1; ++p) {      /* left to right, strict < (R5) */
+                if (p < 0 || p >= W) continue;          /* R4 */
+                int64_t v = m[(size_t)(i - 1) * W + p];
+                if (p == j - 1) v += pix_diff(img, pitch, C, i - 1, j, i, j - 1);  /* CL - CU */
+                if (p == j + 1) v += pix_diff(img, pitch, C, i - 1, j, i, j + 1);  /* CR - CU */
+                if (best < 0 || v < bestv) {
+                    best = p;
+                    bestv = v;
+                }
+            }
+            m[(size_t)i * W + j] = cu + bestv;
+            d[(size_t)i * W + j] = (uint8_t)(best - j + 1);
+        }
+    }
+    int jstar = 0;                                       /* R6 */
+    for (int j = 1; j < W; ++j)
+        if (m[(size_t)(H - 1) * W + j] < m[(size_t)(H - 1) * W + jstar]) jstar = j;
+    *cost = m[(size_t)(H - 1) * W + jstar];
+    seam[H - 1] = jstar;                                 /* R7 */
+    for (int i = H - 1; i >= 1; --i) seam[i - 1] = seam[i] + (int)d[(size_t)i * W + seam[i]] - 1;
+    if (!M) free(m);
+    if (!D) free(d);
+    return SCO_OK;
+}
+
+/*
+ * Forward-energy carve (R9 with R17-R19): W - target_w seams, each the
+ * minimum forward-energy seam of the current image.  Arguments as sco_carve.
+ */
+int sco_carve_forward(uint8_t* img, int H, int W, int C, int pitch, int target_w, int32_t* seams_out,
+                      int64_t* costs_out) {
+    if (!img || H < 1 || W < 1 || C < 1 || pitch < W * C || target_w < 1 || target_w > W) return SCO_EINVAL;
+    int32_t* s = (int32_t*)malloc(sizeof(int32_t) * (size_t)H);
+    if (!s) return SCO_ENOMEM;
+    int rc = SCO_OK;
+    for (int k = 0, w = W; w > target_w; ++k, --w) {
+        int64_t cost = 0;
+        if ((rc = sco_forward_dp(img, H, w, C, pitch, NULL, NULL, s, &cost)) != SCO_OK) break;
+        if ((rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;
+        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);
+        if (costs_out) costs_out[k] = cost;
+    }
+    free(s);
     return rc;
 }
 

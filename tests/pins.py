@@ -353,3 +353,142 @@ def pin_insert_edges(o):
 
 
 ALL_PINS += [pin_insert_hand_grids, pin_insert_sequential_and_invariants, pin_insert_edges]
+
+
+# --------------------------------------------------------------------------------------------
+# Forward energy (sec. "Forward Energy Calculation"; readings R17-R19)
+
+
+def _pair_diff(img, a, b):
+    """D of R17: sum over channels of |I(a) - I(b)|."""
+    return int(np.abs(img[a].astype(np.int64) - img[b].astype(np.int64)).sum())
+
+
+def py_forward_cost_by_removal(img, seam):
+    """Forward cost of removing `seam` from img, from the definition rather than the DP's cases:
+    delete the seam, keep the original coordinates of every remaining pixel, and sum D over each
+    pair that is adjacent in the result (left-right or up-down) but was not adjacent in img.  A
+    seam pixel on the border of its row is charged against the pixel that becomes the border (R18).
+    """
+    img = np.asarray(img)
+    H, W = img.shape[:2]
+    rows = [[x for x in range(W) if x != seam[i]] for i in range(H)]
+    cost = 0
+    for i in range(H):
+        row = rows[i]
+        for x in range(len(row) - 1):
+            if row[x + 1] != row[x] + 1:
+                cost += _pair_diff(img, (i, row[x]), (i, row[x + 1]))
+        if W > 1 and seam[i] in (0, W - 1):
+            cost += _pair_diff(img, (i, seam[i]), (i, 1 if seam[i] == 0 else W - 2))
+        if i > 0:
+            up = rows[i - 1]
+            for x in range(len(row)):
+                if up[x] != row[x]:
+                    cost += _pair_diff(img, (i - 1, up[x]), (i, row[x]))
+    return cost
+
+
+def py_brute_forward(img):
+    """Every connected seam, costed by py_forward_cost_by_removal; the minimum of the key
+    (cost, s[H-1], ..., s[0]) as for the e1 seam (R5, R6).  Tiny images only."""
+    H, W = img.shape[:2]
+    best = None
+    for start in range(W):
+        for moves in itertools.product((-1, 0, 1), repeat=H - 1):
+            path = [start]
+            for mv in moves:
+                path.append(path[-1] + mv)
+            if min(path) < 0 or max(path) >= W:
+                continue
+            key = (py_forward_cost_by_removal(img, path[::-1]), tuple(path))
+            if best is None or key < best:
+                best = key
+    cost, path = best
+    return np.array(path[::-1], np.int32), cost
+
+
+def pin_forward_hand_grids(o):
+    """Grids worked by hand (the M tables, directions, seam and cost in the golden file)."""
+    for g in load_golden("forward_grids.json")["grids"]:
+        img = np.array(g["image"], np.uint8)
+        seam, cost, M, D = o.forward_seam(img, full=True)
+        assert M.tolist() == g["M"], g["name"]
+        assert D[1:].tolist() == g["D"][1:], g["name"]
+        assert seam.tolist() == g["seam"] and cost == g["cost"], g["name"]
+
+
+def pin_forward_bruteforce(o, n=160, seed=21):
+    """DP seam == the exhaustive minimum under the removal-defined cost (tie-heavy inputs)."""
+    rng = np.random.default_rng(seed)
+    for t in range(n):
+        H = int(rng.integers(1, 5))
+        W = int(rng.integers(1, 6))
+        C = int(rng.integers(1, 5))
+        alpha = [2, 3, 5, 256][t % 4]
+        img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+        seam, cost = o.forward_seam(img)
+        bs, bc = py_brute_forward(img)
+        assert (seam.tolist(), cost) == (bs.tolist(), bc), (t, img.tolist())
+
+
+def pin_forward_closed_forms(o):
+    rng = np.random.default_rng(22)
+    # constant image: every removal creates pairs of equal pixels
+    img = np.full((5, 8, 3), 40, np.uint8)
+    out, seams, costs = o.carve_forward(img, 3)
+    assert np.all(seams == 0) and np.all(costs == 0) and np.array_equal(out, img[:, :3])
+    # identical rows: vertical pairs of a straight seam are old pairs, so the cheapest seam is the
+    # straight one at the leftmost minimum of the row's horizontal cost, and it costs H times that
+    for _ in range(20):
+        H, W, C = int(rng.integers(1, 7)), int(rng.integers(2, 9)), int(rng.integers(1, 5))
+        row = rng.integers(0, 6, size=(1, W, C), dtype=np.uint8)
+        img = np.repeat(row, H, axis=0)
+        cu = [_pair_diff(row[0], max(j - 1, 0), min(j + 1, W - 1)) for j in range(W)]
+        seam, cost = o.forward_seam(img)
+        assert seam.tolist() == [int(np.argmin(cu))] * H and cost == H * min(cu), (row.tolist(), cu)
+    # one row: the leftmost minimum of CU
+    for _ in range(20):
+        row = rng.integers(0, 256, size=(1, 7, 3), dtype=np.uint8)
+        cu = [_pair_diff(row[0], max(j - 1, 0), min(j + 1, 6)) for j in range(7)]
+        seam, cost = o.forward_seam(row)
+        assert seam[0] == int(np.argmin(cu)) and cost == min(cu)
+    # one column: nothing to remove against, cost 0
+    seam, cost = o.forward_seam(rng.integers(0, 256, size=(6, 1, 3), dtype=np.uint8))
+    assert seam.tolist() == [0] * 6 and cost == 0
+    # target_w == W is the identity
+    img = rng.integers(0, 256, size=(4, 5, 3), dtype=np.uint8)
+    out, seams, costs = o.carve_forward(img, 5)
+    assert np.array_equal(out, img) and seams.shape == (0, 4)
+
+
+def forward_carve_invariants(o, img, target_w, check_brute=False):
+    """Run the forward carve seam by seam: each seam is valid, its recorded cost is the
+    removal-defined cost on the current image, it is the current image's minimum seam, and the
+    output is the input with the seams deleted."""
+    out, seams, costs = o.carve_forward(img, target_w)
+    cur = img.copy()
+    H = img.shape[0]
+    for k in range(seams.shape[0]):
+        s = seams[k]
+        check_seam_valid(s, H, cur.shape[1])
+        assert costs[k] == py_forward_cost_by_removal(cur, s), ("cost", k)
+        if check_brute:
+            bs, bc = py_brute_forward(cur)
+            assert s.tolist() == bs.tolist() and costs[k] == bc, ("brute", k)
+        cur = np.stack([np.delete(cur[i], s[i], axis=0) for i in range(H)])
+    assert np.array_equal(out, cur), "carved image != input with the seams deleted"
+    return seams, costs
+
+
+def pin_forward_carve_invariants(o):
+    rng = np.random.default_rng(23)
+    for (H, W, C, tw) in [(4, 6, 3, 2), (3, 5, 1, 1), (1, 6, 4, 2), (5, 2, 3, 1)]:
+        for alpha in (3, 256):
+            img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+            forward_carve_invariants(o, img, tw, check_brute=True)
+    img = rng.integers(0, 256, size=(12, 20, 3), dtype=np.uint8)
+    forward_carve_invariants(o, img, 9)
+
+
+ALL_PINS += [pin_forward_hand_grids, pin_forward_bruteforce, pin_forward_closed_forms, pin_forward_carve_invariants]

@@ -51,6 +51,20 @@ MUTANTS = {
         "if (e[(size_t)(H - 1) * W + j] < e[(size_t)(H - 1) * W + start]) start = j;",
         "if (e[(size_t)(H - 1) * W + j] <= e[(size_t)(H - 1) * W + start]) start = j;"),
     "brute_keeps_last_tie": ("if (!c->have || acc < c->best_cost) {", "if (!c->have || acc <= c->best_cost) {"),
+    "forward_left_term_wrong_row": (
+        "if (p == j - 1) v += pix_diff(img, pitch, C, i - 1, j, i, j - 1);",
+        "if (p == j - 1) v += pix_diff(img, pitch, C, i, j, i, j - 1);"),
+    "forward_side_terms_swapped": (
+        "if (p == j - 1) v += pix_diff(img, pitch, C, i - 1, j, i, j - 1);",
+        "if (p == j - 1) v += pix_diff(img, pitch, C, i - 1, j, i, j + 1);"),
+    "forward_border_uncharged": (
+        "int64_t cu = pix_diff(img, pitch, C, i, clampi(j - 1, 0, W - 1), i, clampi(j + 1, 0, W - 1));",
+        "int64_t cu = (j > 0 && j < W - 1) ? pix_diff(img, pitch, C, i, j - 1, i, j + 1) : 0;"),
+    "forward_first_row_zero": ("                m[j] = cu;\n", "                m[j] = 0;\n"),
+    "forward_tie_rightmost": ("if (best < 0 || v < bestv) {", "if (best < 0 || v <= bestv) {"),
+    "forward_carve_never_removes": (
+        "if ((rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;\n        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);\n        if (costs_out) costs_out[k] = cost;\n    }\n    free(s);",
+        "if (k < 0 && (rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;\n        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);\n        if (costs_out) costs_out[k] = cost;\n    }\n    free(s);"),
     "transpose_swaps_nothing": (
         "dst[(size_t)x * dpitch + (size_t)y * C + c] = src[(size_t)y * spitch + (size_t)x * C + c];",
         "dst[(size_t)x * dpitch + (size_t)y * C + c] = src[(size_t)(y % W) * spitch + (size_t)(x % H) * C + c];"),
