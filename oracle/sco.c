@@ -325,12 +325,13 @@ int sco_forward_dp(const uint8_t* img, int H, int W, int C, int pitch, int64_t* 
             d[(size_t)i * W + j] = (uint8_t)(best - j + 1);
         }
     }
-    int jstar = 0;                                       /* R6 */
+    const int64_t* last = m + (size_t)(H - 1) * W;
+    int jstar = 0;                                       /* R6: the first minimum */
     for (int j = 1; j < W; ++j)
-        if (m[(size_t)(H - 1) * W + j] < m[(size_t)(H - 1) * W + jstar]) jstar = j;
-    *cost = m[(size_t)(H - 1) * W + jstar];
+        if (last[j] < last[jstar]) jstar = j;
+    *cost = last[jstar];
     seam[H - 1] = jstar;                                 /* R7 */
-    for (int i = H - 1; i >= 1; --i) seam[i - 1] = seam[i] + (int)d[(size_t)i * W + seam[i]] - 1;
+    for (int i = H - 1; i > 0; --i) seam[i - 1] = seam[i] - 1 + (int)d[(size_t)i * W + seam[i]];
     if (!M) free(m);
     if (!D) free(d);
     return SCO_OK;

@@ -61,6 +61,10 @@ MUTANTS = {
         "int64_t cu = pix_diff(img, pitch, C, i, clampi(j - 1, 0, W - 1), i, clampi(j + 1, 0, W - 1));",
         "int64_t cu = (j > 0 && j < W - 1) ? pix_diff(img, pitch, C, i, j - 1, i, j + 1) : 0;"),
     "forward_first_row_zero": ("                m[j] = cu;\n", "                m[j] = 0;\n"),
+    "forward_last_row_tie_rightmost": ("if (last[j] < last[jstar]) jstar = j;", "if (last[j] <= last[jstar]) jstar = j;"),
+    "forward_backtrack_reads_wrong_row": (
+        "seam[i - 1] = seam[i] - 1 + (int)d[(size_t)i * W + seam[i]];",
+        "seam[i - 1] = seam[i] - 1 + (int)d[(size_t)(i - 1) * W + seam[i]];"),
     "forward_tie_rightmost": ("if (best < 0 || v < bestv) {", "if (best < 0 || v <= bestv) {"),
     "forward_carve_never_removes": (
         "if ((rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;\n        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);\n        if (costs_out) costs_out[k] = cost;\n    }\n    free(s);",
