@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward"], default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
                          "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal); "
                          "insert: 1920x1080 widened by 480 seams; sweep: the paper's size sweep of square "
@@ -130,6 +130,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}), flush=True)
+        return
+    if args.workload == "forward":
+        forward(args, dev)
         return
     if args.workload != "batch":
         single(args, dev)
@@ -494,7 +497,73 @@ def cpu_brute_sweep():
     return {"sizes": out, "fit_log_base_of_T_over_n_10_12": round(out_fit, 3), "log_3": round(float(np.log(3)), 3)}
 
 
-def cpu_baseline(jobs, imgs_np, gpu_results, seconds):
+def forward_byte_model(H: int, W: int, C: int, k: int) -> int:
+    """Algorithmic HBM bytes of k forward-energy seams of an H x W x C image, one seam at a time:
+    the DP reads the current image once (H*w*C) and writes the 2-bit direction map (H*w/4); the
+    removal moves the pixels right of the seam, on average half a row each way (H*w*C)."""
+    return sum(H * w * C + H * w // 4 + H * w * C for w in range(W, W - k, -1))
+
+
+def forward(args, dev):
+    """Forward-energy carve (sec. "Forward Energy Calculation") of the batched workload: the same
+    256 images as the default benchmark, one 1024-thread workgroup per image."""
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    jobs = synth.batch_jobs(n=args.n)
+    imgs_np = [j.image() for j in jobs]
+    srcs = [torch.from_numpy(a).to(dev) for a in imgs_np]
+    dsts = [torch.empty_like(s) for s in srcs]
+    pixel_seams = sum(j.pixel_seams for j in jobs)
+    fb = api.ForwardBatch(dsts, [j.target_w for j in jobs], srcs=srcs)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        fb.launch()
+        torch.cuda.synchronize()
+        log(f"warmup {i} done")
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        events[i][0].record(stream)
+        fb.launch_copy()
+        events[i][1].record(stream)
+        fb.launch_carve()
+        events[i][2].record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1000.0 / args.steps
+    copy_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    carve_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    times = fb.times()
+    t_first = min(tb for tb, _ in times)
+    lat_ms = [(te - t_first) * 1000.0 for _, te in times]
+    longest = int(np.argmax([te - tb for tb, te in times]))
+    model_bytes = sum(forward_byte_model(j.h, j.w, 3, j.seams) for j in jobs)
+    achieved = model_bytes / (carve_ms / 1000.0) / 1e9
+    out = {
+        "metric": METRIC, "value": round(pixel_seams / (ms_per_step / 1000.0), 1), "unit": "pixel-seams/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"forward-energy batched carve: {len(jobs)} RGB uint8 blob+noise images, "
+                               "H,W~U[240,2160], 10-40% of width removed (seed 3)",
+                   "images": len(jobs), "pixel_seams": pixel_seams},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "fwd_carve_kernel",
+                     "model_bytes_per_launch": model_bytes, "kernel_ms": round(carve_ms, 3)},
+        "copy_pass_ms": round(copy_ms, 3),
+        "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
+                       "max": round(max(lat_ms), 2)},
+        "longest_image": {"h": jobs[longest].h, "w": jobs[longest].w, "seams": jobs[longest].seams,
+                          "run_ms": round((times[longest][1] - times[longest][0]) * 1000.0, 1)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, fb.results(), args.cpu_seconds, forward=True)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False):
     """The oracle, as it stands, on a bounded sample of the same workload on the host cores."""
     from concurrent.futures import ThreadPoolExecutor
 
@@ -505,8 +574,8 @@ def cpu_baseline(jobs, imgs_np, gpu_results, seconds):
     except AttributeError:  # pragma: no cover
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    # sample: the images in job order, up to ~seconds of work per core at ~1e8 pixel-seams/s per core
-    budget = seconds * 1e8 * cores
+    # sample: the images in job order, up to ~seconds of work per core at the oracle's usual rate
+    budget = seconds * (3e7 if forward else 1e8) * cores  # the forward oracle does three pair sums per cell
     idx, acc = [], 0
     for i, j in enumerate(jobs):
         if acc + j.pixel_seams > budget and idx:
@@ -518,6 +587,8 @@ def cpu_baseline(jobs, imgs_np, gpu_results, seconds):
     oracle.default()
 
     def run(i):
+        if forward:
+            return oracle.carve_forward(imgs_np[i], jobs[i].target_w)
         return oracle.carve(imgs_np[i], jobs[i].target_w)
 
     t = time.perf_counter()

@@ -221,6 +221,43 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
                          void* stream);
 
 /*
+ * Forward energy (sec. "Forward Energy Calculation": the cost of a seam is the
+ * energy of the pixel pairs its removal makes neighbours).  The DP of Alg. 3
+ * runs with the per-pixel energy replaced by those costs:
+ *   CU(i,j) = D((i,j-1),(i,j+1)),
+ *   M(i,j)  = min(M(i-1,j-1) + CU + D((i-1,j),(i,j-1)),
+ *                 M(i-1,j)   + CU,
+ *                 M(i-1,j+1) + CU + D((i-1,j),(i,j+1))),   M(0,j) = CU(0,j),
+ * where D(p,q) is the sum over channels of |I(p)-I(q)| and a column index
+ * outside the row is clamped to it (so a border pixel costs its difference to
+ * the pixel that becomes the border).  Ties, backtrack, removal and the seam
+ * loop are those of sc_carve; the costs are recomputed from the current pixels
+ * for every seam.  One 1024-thread workgroup carves one image.
+ *
+ * sc_carve_forward: arguments as sc_carve (no tune); seams_out/costs_out
+ *   (nullable) receive every seam and its forward cost.  ws: at least
+ *   sc_forward_workspace_bytes(H, W, C) bytes, 256-byte aligned.
+ * Batches: sc_forward_batch_prepare validates the jobs and writes the image
+ *   descriptors into ws with a synchronous copy (ws: at least
+ *   sc_forward_batch_workspace_bytes(jobs, n) bytes); sc_forward_batch_launch
+ *   enqueues the copy-in pass and the carve (no allocation, no host copy; the
+ *   info must come from sc_forward_batch_prepare).  Per-image clocks:
+ *   sc_read_times on the same ws.
+ * Limits: those of sc_carve, plus W <= 8192 and H*roundup(W*C, 64) < 2^31.
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EUNSUPPORTED, SC_EHIP.
+ */
+size_t sc_forward_workspace_bytes(int H, int W, int C);
+sc_status sc_carve_forward(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
+                           int32_t* seams_out, int64_t* costs_out, void* ws, size_t ws_bytes, void* stream);
+size_t sc_forward_batch_workspace_bytes(const sc_job* jobs, int n);
+sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* ws, size_t ws_bytes, sc_batch_info* info);
+sc_status sc_forward_batch_launch(const sc_batch_info* info, void* ws, void* stream);
+/* The two passes of sc_forward_batch_launch, for callers that time them apart: the copy-in pass
+ * (zero control words, copy src -> img and into the working copy) and the carve. */
+sc_status sc_forward_batch_launch_copy(const sc_batch_info* info, void* ws, void* stream);
+sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream);
+
+/*
  * Step-wise carving for a serving loop (continuous batching).  A slot table (device memory,
  * sc_slot_table_bytes(n) bytes, caller-owned) holds one image per slot; each image keeps its own
  * workspace (sc_workspace_bytes) and stays on the device between steps.

@@ -57,6 +57,13 @@ SIGNATURES = {
     "sc_batch_launch_energy": (I, [ctypes.POINTER(sc_batch_info), P, P]),
     "sc_batch_launch_carve": (I, [ctypes.POINTER(sc_batch_info), P, P]),
     "sc_carve_batch": (I, [ctypes.POINTER(sc_job), I, ctypes.POINTER(sc_tune), P, Z, P]),
+    "sc_forward_workspace_bytes": (Z, [I, I, I]),
+    "sc_carve_forward": (I, [P, P, I, I, I, I, I, P, P, P, Z, P]),
+    "sc_forward_batch_workspace_bytes": (Z, [ctypes.POINTER(sc_job), I]),
+    "sc_forward_batch_prepare": (I, [ctypes.POINTER(sc_job), I, P, Z, ctypes.POINTER(sc_batch_info)]),
+    "sc_forward_batch_launch": (I, [ctypes.POINTER(sc_batch_info), P, P]),
+    "sc_forward_batch_launch_copy": (I, [ctypes.POINTER(sc_batch_info), P, P]),
+    "sc_forward_batch_launch_carve": (I, [ctypes.POINTER(sc_batch_info), P, P]),
     "sc_read_status": (I, [P, ctypes.POINTER(ctypes.c_uint32), I]),
     "sc_read_times": (I, [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), I,
                           ctypes.POINTER(ctypes.c_double)]),

@@ -141,6 +141,28 @@ def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, rec
     return img[:, : int(target_w)], seams, costs
 
 
+def carve_forward(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,
+                  ws: torch.Tensor | None = None, stream=None):
+    """Carve `img` to target_w columns with forward-energy seams (in place; from `src` when given).
+
+    Returns (img[:, :target_w], seams int32 [k, H] or None, costs int64 [k] or None).
+    """
+    H, W, C, pitch = _image(img)
+    if src is not None and _image(src, "src") != (H, W, C, pitch):
+        raise ValueError("src must have the shape and pitch of img")
+    k = W - int(target_w)
+    need = _lib.load().sc_forward_workspace_bytes(H, W, C)
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, img.device)
+    seams = costs = None
+    if record and k > 0:
+        seams = torch.empty((k, H), dtype=torch.int32, device=img.device)
+        costs = torch.empty(k, dtype=torch.int64, device=img.device)
+    _lib.call("sc_carve_forward", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
+              _ptr(ws), ws.numel(), _stream(stream))
+    return img[:, : int(target_w)], seams, costs
+
+
 def insert_seams(img: torch.Tensor, k: int, out: torch.Tensor | None = None, record: bool = True,
                  team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None):
     """Widen `img` by k seams (img is not modified).
@@ -315,3 +337,56 @@ class BatchCarver:
 
     def status(self):
         return read_status(self.ws, len(self.jobs))
+
+
+class ForwardBatch:
+    """Forward-energy carve of many images of uneven sizes, one workgroup per image.
+
+    ``prepare()`` uploads the image descriptors (synchronous); ``launch()`` enqueues the copy-in
+    pass and the carve with no host-to-device copy and no allocation.
+    """
+
+    def __init__(self, imgs, targets, srcs=None, record: bool = True):
+        self.jobs = []
+        for i, (img, tw) in enumerate(zip(imgs, targets)):
+            H, W, C, pitch = _image(img)
+            src = None if srcs is None else srcs[i]
+            if src is not None and _image(src, "src") != (H, W, C, pitch):
+                raise ValueError("src must have the shape and pitch of img")
+            k = W - int(tw)
+            seams = torch.empty((k, H), dtype=torch.int32, device=img.device) if record and k > 0 else None
+            costs = torch.empty(k, dtype=torch.int64, device=img.device) if record and k > 0 else None
+            self.jobs.append(_Job(src, img, int(tw), seams, costs))
+        n = len(self.jobs)
+        self._cjobs = (_lib.sc_job * n)()
+        for i, j in enumerate(self.jobs):
+            H, W, C, pitch = _image(j.img)
+            self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
+                                         pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
+                                         None if j.costs is None else j.costs.data_ptr())
+        need = _lib.load().sc_forward_batch_workspace_bytes(self._cjobs, n)
+        if need == 0:
+            raise ValueError("bad batch")
+        self.ws = workspace(need, self.jobs[0].img.device)
+        self.info = _lib.sc_batch_info()
+        self.prepare()
+
+    def prepare(self):
+        _lib.call("sc_forward_batch_prepare", self._cjobs, len(self.jobs), _ptr(self.ws), self.ws.numel(),
+                  ctypes.byref(self.info))
+
+    def launch(self, stream=None):
+        _lib.call("sc_forward_batch_launch", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def launch_copy(self, stream=None):
+        _lib.call("sc_forward_batch_launch_copy", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def launch_carve(self, stream=None):
+        _lib.call("sc_forward_batch_launch_carve", ctypes.byref(self.info), _ptr(self.ws), _stream(stream))
+
+    def times(self):
+        """Per-image (begin, end) of the last carve in seconds of the device clock."""
+        return read_times(self.ws, len(self.jobs))
+
+    def results(self):
+        return [(j.img[:, : j.target_w], j.seams, j.costs) for j in self.jobs]

@@ -464,7 +464,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
 }
 
 static sc_status batch_pass(const sc_batch_info* info, void* ws, void* stream, bool energy, bool carve) {
-    if (!info || !ws || info->n < 1 || info->nblocks < 1) return fail(SC_EINVAL, "bad batch info");
+    if (!info || !ws || info->n < 1 || info->nblocks < 1 || info->team < 1) return fail(SC_EINVAL, "bad batch info");
     char* base = static_cast<char*>(ws);
     hipStream_t st = (hipStream_t)stream;
     const sc::Img* imgs = reinterpret_cast<const sc::Img*>(base + info->off_imgs);
@@ -643,4 +643,195 @@ extern "C" sc_status sc_slots_step_timed(const void* table, int n_slots, int max
                                           (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "slot step");
     return ok();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward energy (sec. "Forward Energy Calculation"): one workgroup per image, no energy plane.
+namespace {
+
+struct FwdLayout {
+    size_t dirs, anc, seam, ro, wk, total;
+    int db, wp;
+};
+
+FwdLayout fwd_layout(int H, int W, int C) {
+    FwdLayout L;
+    const int P = (H + sc::kFwdPhaseRows - 1) / sc::kFwdPhaseRows;
+    L.db = (int)sc::align_up((size_t)(W + 3) / 4, 16);  // direction bytes (4 columns each) per row
+    L.wp = (int)sc::align_up((size_t)W * C, 64);
+    size_t off = 0;
+    L.dirs = off;
+    off = sc::align_up(off + (size_t)((H + 3) / 4) * L.db * 4, sc::kAlign);  // rows grouped by four
+    L.anc = off;  // phase ancestors, used when they do not fit in LDS
+    off = sc::align_up(off + (size_t)P * W, sc::kAlign);
+    L.seam = off;
+    off = sc::align_up(off + (size_t)H * 4, sc::kAlign);
+    L.ro = off;
+    off = sc::align_up(off + (size_t)H * 4, sc::kAlign);
+    L.wk = off;
+    off = sc::align_up(off + (size_t)H * L.wp + sc::kFwdSlack, sc::kAlign);
+    L.total = off;
+    return L;
+}
+
+sc_status check_fwd_image(int H, int W, int C, int pitch) {
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (W > sc::kFwdMaxW) return fail(SC_EUNSUPPORTED, "W=%d > %d (forward energy)", W, sc::kFwdMaxW);
+    if ((long long)H * (long long)sc::align_up((size_t)W * C, 64) + (long long)sc::kFwdSlack >= (1ll << 31))
+        return fail(SC_EUNSUPPORTED, "image of %lld bytes too large for the forward-energy path",
+                    (long long)H * W * C);
+    return SC_OK;
+}
+
+sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
+                     int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl) {
+    const FwdLayout L = fwd_layout(H, W, C);
+    sc::Img d;
+    memset(&d, 0, sizeof(d));
+    d.src = src;
+    d.img = img;
+    d.pitch = pitch;
+    d.H = H;
+    d.W = W;
+    d.C = C;
+    d.target_w = target_w;
+    d.seams_out = seams_out;
+    d.costs_out = reinterpret_cast<long long*>(costs_out);
+    d.dirs = reinterpret_cast<uint8_t*>(base + L.dirs);
+    d.anc = reinterpret_cast<int8_t*>(base + L.anc);
+    d.seam = reinterpret_cast<int32_t*>(base + L.seam);
+    d.ro = reinterpret_cast<int32_t*>(base + L.ro);
+    d.wk = reinterpret_cast<uint8_t*>(base + L.wk);
+    d.wp = L.wp;
+    d.db = L.db;
+    d.amin = &ctl->amin;
+    d.bar = &ctl->bar;
+    d.status = &ctl->status;
+    d.G = 1;
+    return d;
+}
+
+double fwd_work(const sc_job& j) {  // pixel-seams: rows times the widths the seams are taken from
+    const double k = j.W - j.target_w;
+    return (double)j.H * k * (j.W + j.target_w + 1) / 2.0;
+}
+
+}  // namespace
+
+extern "C" size_t sc_forward_workspace_bytes(int H, int W, int C) {
+    if (H < 1 || W < 1 || C < 1 || C > 4) return 0;
+    return ctl_region(1) + fwd_layout(H, W, C).total;
+}
+
+extern "C" sc_status sc_carve_forward(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
+                                      int32_t* seams_out, int64_t* costs_out, void* ws, size_t ws_bytes,
+                                      void* stream) {
+    sc_status s = check_fwd_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    if (!img || !ws) return fail(SC_EINVAL, "null pointer");
+    if (target_w < 1 || target_w > W) return fail(SC_EINVAL, "target_w=%d not in [1, W=%d]", target_w, W);
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const size_t need = sc_forward_workspace_bytes(H, W, C);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    char* base = static_cast<char*>(ws);
+    sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
+    const sc::Img d = make_fwd_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out, base + ctl_region(1), ctl);
+    hipStream_t st = (hipStream_t)stream;
+    // the prepare pass also writes the descriptor into the workspace header, where the carve reads it
+    hipError_t e = sc::launch_prepare_single(d, st);
+    if (e == hipSuccess && target_w < W)
+        e = sc::launch_fwd_carve(reinterpret_cast<const sc::Img*>(base + sc::kWsImgOffset), nullptr, 1, W, st);
+    if (e != hipSuccess) return hip_fail(e, "forward carve launch");
+    return ok();
+}
+
+extern "C" size_t sc_forward_batch_workspace_bytes(const sc_job* jobs, int n) {
+    if (!jobs || n < 1) return 0;
+    size_t total = ctl_region(n);
+    total += sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
+    total += sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].H < 1 || jobs[i].W < 1 || jobs[i].C < 1 || jobs[i].C > 4) return 0;
+        total += fwd_layout(jobs[i].H, jobs[i].W, jobs[i].C).total;
+    }
+    return total;
+}
+
+extern "C" sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* ws, size_t ws_bytes,
+                                              sc_batch_info* info) {
+    if (!jobs || n < 1 || !ws || !info) return fail(SC_EINVAL, "null pointer or n < 1");
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    int max_w = 1, max_rows = 1;
+    for (int i = 0; i < n; ++i) {
+        const sc_job& j = jobs[i];
+        sc_status s = check_fwd_image(j.H, j.W, j.C, j.pitch);
+        if (s != SC_OK) return fail(s, "job %d: %s", i, g_err);
+        if (!j.img) return fail(SC_EINVAL, "job %d: null image", i);
+        if (j.target_w < 1 || j.target_w > j.W)
+            return fail(SC_EINVAL, "job %d: target_w=%d not in [1, %d]", i, j.target_w, j.W);
+        max_w = std::max(max_w, j.W);
+        max_rows = std::max(max_rows, j.H);
+    }
+    const size_t need = sc_forward_batch_workspace_bytes(jobs, n);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    const size_t off_imgs = ctl_region(n);
+    const size_t off_order = off_imgs + sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
+    size_t off_data = off_order + sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    std::vector<char> host(off_data, 0);
+    WsHead* h = reinterpret_cast<WsHead*>(host.data());
+    h->magic = kMagic;
+    h->n = n;
+    char* base = static_cast<char*>(ws);
+    sc::Img* imgs = reinterpret_cast<sc::Img*>(host.data() + off_imgs);
+    for (int i = 0; i < n; ++i) {
+        const sc_job& j = jobs[i];
+        sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead)) + i;
+        imgs[i] = make_fwd_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
+                               base + off_data, ctl);
+        off_data += fwd_layout(j.H, j.W, j.C).total;
+    }
+    // workgroups start in order of decreasing work, so the longest carves never wait for a slot
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fwd_work(jobs[a]) > fwd_work(jobs[b]); });
+    memcpy(host.data() + off_order, order.data(), n * sizeof(int));
+    hipError_t e = hipMemcpy(ws, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "forward batch upload");
+    memset(info, 0, sizeof(*info));
+    info->n = n;
+    info->nblocks = n;
+    info->variant = max_w;  // widest image: selects the columns per thread
+    info->max_rows = max_rows;
+    info->team = 0;         // marks a forward-energy batch
+    info->off_imgs = off_imgs;
+    info->off_blk = off_order;
+    return ok();
+}
+
+static sc_status fwd_batch_pass(const sc_batch_info* info, void* ws, void* stream, bool copy, bool carve) {
+    if (!info || !ws || info->n < 1 || info->nblocks != info->n || info->team != 0 || info->variant < 1 ||
+        info->variant > sc::kFwdMaxW)
+        return fail(SC_EINVAL, "not a forward-energy batch");
+    char* base = static_cast<char*>(ws);
+    const sc::Img* imgs = reinterpret_cast<const sc::Img*>(base + info->off_imgs);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (copy) e = sc::launch_prepare_batch(imgs, info->n, info->max_rows, st);
+    if (e == hipSuccess && carve)
+        e = sc::launch_fwd_carve(imgs, reinterpret_cast<const int*>(base + info->off_blk), info->n, info->variant, st);
+    if (e != hipSuccess) return hip_fail(e, "forward batch launch");
+    return ok();
+}
+
+extern "C" sc_status sc_forward_batch_launch(const sc_batch_info* info, void* ws, void* stream) {
+    return fwd_batch_pass(info, ws, stream, true, true);
+}
+
+extern "C" sc_status sc_forward_batch_launch_copy(const sc_batch_info* info, void* ws, void* stream) {
+    return fwd_batch_pass(info, ws, stream, true, false);
+}
+
+extern "C" sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream) {
+    return fwd_batch_pass(info, ws, stream, false, true);
 }

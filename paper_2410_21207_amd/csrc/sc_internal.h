@@ -96,4 +96,12 @@ hipError_t launch_insert_seams(const uint8_t* img, int H, int W, int C, long lon
                                uint8_t* out, long long out_pitch, hipStream_t st);
 constexpr int kInsertMaxWidth = 65536;
 
+// Forward-energy carve (one 1024-thread workgroup per image).  Widths up to 4096 use 4 columns per
+// thread, up to kFwdMaxW 8.  Loads of a row may read up to kFwdSlack bytes past the last row of wk.
+constexpr int kFwdMaxW = 8192;
+constexpr int kFwdMaxH = 16448;
+constexpr int kFwdPhaseRows = 60;  // rows per backtrack phase of the forward DP
+constexpr size_t kFwdSlack = 256;
+hipError_t launch_fwd_carve(const Img* imgs, const int* order, int n, int max_w, hipStream_t st);
+
 }  // namespace sc

@@ -27,6 +27,7 @@
 //    the energy is then recomputed only at the two new columns {s-1, s} of
 //    each row (the only cells whose stencil changed).
 #include <type_traits>
+#include <utility>
 
 #include "sc_internal.h"
 
@@ -168,12 +169,12 @@ __device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
     }
     for (int y = row_begin; y < d.H; y += row_step) {
         if (threadIdx.x == 0) *gp(d.ro + y) = 0;
-        uint16_t* er = d.e + (long long)y * d.ep;
+        uint16_t* er = d.e ? d.e + (long long)y * d.ep : nullptr;  // no energy plane: forward energy
         const uint8_t* s = srcimg + (long long)y * d.pitch;
         uint8_t* wr = d.wk + (long long)y * d.wp;
         uint8_t* o = d.img + (long long)y * d.pitch;
         for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
-            *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
+            if (d.e) *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
             for (int c = 0; c < d.C; ++c) {
                 const uint8_t v = *gp(s + x * d.C + c);
                 *gp(wr + x * d.C + c) = v;
@@ -1238,6 +1239,326 @@ __global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint
 }
 
 // ----------------------------------------------------------------------------------------------
+// Forward energy (sec. "Forward Energy Calculation", the standard definition with no per-pixel
+// term): the DP cost of removing pixel (i,j) is the difference of the pixel pairs its removal
+// makes neighbours, CU = D(left, right), plus D(up, left) when the seam comes from the upper-left
+// parent or D(up, right) from the upper-right one.  D sums |difference| over the channels (one
+// v_sad_u8 on packed pixels) and a neighbour index outside the row is clamped to it.  The costs
+// come from the current pixels, so there is no energy plane and no band update: every row of the
+// DP reads two rows of the working copy.
+//
+// One workgroup of 1024 threads carves one image; thread t owns columns [CPL*t, CPL*t + CPL).
+// Between rows a column's state is one word M << 9 | a, a = 64 + (ancestor column in the last
+// row before the current K-row phase) - (column).  A row forms three candidate words per column
+// (upper-left, up, upper-right: tags 0, 1, 2 in bits 7-8, pair costs added to M) and one
+// v_min3_u32 picks the cheapest with ties to the leftmost parent, carrying the parent's ancestor
+// offset along.  M <= 255*C*H < 2^23 under the library's limit H*510*C <= 8388000.  Neighbour
+// states cross threads through LDS with one barrier per row (LDS-only fences: the pixel rows
+// loaded PF rows ahead stay in flight).  At the end of each phase the ancestor offsets go to LDS
+// (to the workspace when they do not fit), so the backtrack hops phase by phase and then walks
+// the K rows of every phase in parallel from an LDS window of the 2-bit direction map.  Removal
+// moves the pixels right of the seam one column left with the in-place slot shifter.
+// Calls f(std::integral_constant<int, 0>{}) ... f(std::integral_constant<int, N-1>{}) in order.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+namespace fwd {
+constexpr int NT = 1024;
+constexpr int NW = NT / 64;
+constexpr int K = kFwdPhaseRows;            // rows per phase: the ancestor offset stays in [4, 124]
+constexpr int GK = K / 4;                   // 4-row direction groups per phase
+constexpr int WD = 32;                      // window dwords per group: columns je-59 .. je+59
+constexpr int PF = 8;                       // rows of pixels loaded ahead
+constexpr int PMAX = (kFwdMaxH + K - 1) / K;
+constexpr int ANC_LDS = 96 * 1024;          // phase ancestors kept in LDS up to this many bytes
+constexpr uint32_t INF = 0xFFFFFFFFu;
+static_assert(K % 4 == 0 && K <= 63 && PF % 4 == 0, "phase shape");
+
+struct Smem {
+    uint32_t xa[2][NT + 1];  // first column state of thread t at [t]
+    uint32_t xb[2][NT + 1];  // last column state of thread t at [t + 1]
+    uint32_t win[NW][GK * WD];
+    int jend[PMAX];          // seam column at the last row of every phase
+    unsigned long long red[NW];
+    uint8_t anc[ANC_LDS];
+};
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int C, int CPL>
+struct Carver {
+    // A thread reads the dwords covering columns j0-1 .. j0+CPL of a row: they start at byte
+    // j0*C - 4 (j0*C is a multiple of 4 because CPL is), where column j0-1 sits at byte LEAD.
+    static constexpr int LEAD = (4 - C % 4) % 4;
+    static constexpr int NDW = (LEAD + (CPL + 2) * C + 3) / 4;
+    static constexpr uint32_t PMASK = C == 4 ? 0xFFFFFFFFu : (1u << (8 * C)) - 1u;
+    static_assert(CPL % 4 == 0, "a thread's directions fill whole bytes");
+
+    // vl: byte offset of the dword left of column j0 (it holds only column j0-1); v0: of column j0.
+    // Either is kBufDrop where nothing may be read (the load then returns 0).
+    static __device__ __forceinline__ void load_row(uint32_t (&v)[NDW], __amdgpu_buffer_rsrc_t r, uint32_t vl,
+                                                    uint32_t v0, uint32_t soff) {
+        v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)vl, (int)soff, 0);
+#pragma unroll
+        for (int q = 1; q < NDW; ++q) v[q] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(v0 + 4u * (q - 1)), (int)soff, 0);
+    }
+
+    // pixel k (column j0-1+k) of a loaded row, channels packed in the low bytes
+    static __device__ __forceinline__ void pixels(const uint32_t (&v)[NDW], uint32_t (&p)[CPL + 2]) {
+#pragma unroll
+        for (int k = 0; k < CPL + 2; ++k) {
+            const int o = LEAD + C * k, q = o >> 2, r = o & 3;
+            uint32_t x;
+            if (r == 0) x = v[q];
+            else if (r + C <= 4) x = v[q] >> (8 * r);
+            else x = __builtin_amdgcn_alignbyte(v[q + 1], v[q], (uint32_t)r);
+            p[k] = x & PMASK;
+        }
+    }
+
+    static __device__ __forceinline__ void carve(const Img& d, Smem& sm) {
+        const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+        const int H = d.H, j0 = t * CPL;
+        const int nseams = d.W - d.target_w;
+        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        if (t == 0) ctl->t_begin = wall_clock64();
+        const __amdgpu_buffer_rsrc_t rwk = make_rsrc(d.wk, (uint32_t)H * (uint32_t)d.wp + (uint32_t)kFwdSlack);
+        const uint32_t gbytes = (uint32_t)d.db * 4u;  // bytes of one 4-row group of the direction map
+        const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * gbytes);
+        const int P = (H + K - 1) / K;
+        int w = d.W;
+#pragma unroll 1
+        for (int k = 0; k < nseams; ++k, --w) {
+            const bool act = j0 < w;
+            // per-lane byte offsets of column j0 and of the dword left of it in a row; dropped for
+            // idle threads and left of column 0 (that neighbour is clamped to column 0 below)
+            const uint32_t v0 = act ? (uint32_t)(j0 * C) : kBufDrop;
+            const uint32_t vl = act && j0 > 0 ? (uint32_t)(j0 * C - 4) : kBufDrop;
+            // phase ancestors: LDS, or the workspace when they do not fit.  Two explicit paths, not
+            // one generic pointer: a flat store would make every later LDS wait also wait for the
+            // pixel loads in flight.
+            const bool anc_lds = P * w <= ANC_LDS;
+            uint8_t* const ancg = reinterpret_cast<uint8_t*>(d.anc);
+            bool okR[CPL];  // column j0+c has a right neighbour
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) okR[c] = j0 + c + 1 < w;
+
+            // ---- DP over the rows (a3 with forward costs)
+            // Rows go in blocks of PF with the ring slot of a row refilled right after its pixels
+            // are taken.  The refills of full blocks are unconditional (clamped to the last row),
+            // so no ring register is merged across a branch: a merge would need a copy of a
+            // register whose load is still in flight, i.e. a wait for every outstanding load.
+            uint32_t ring[PF][NDW];
+            static_for<PF>([&](auto U) {
+                constexpr int u = decltype(U)::value;
+                load_row(ring[u], rwk, vl, v0, (uint32_t)min(u, H - 1) * (uint32_t)d.wp);
+            });
+            uint32_t S[CPL], Pup[CPL], dacc[CPL / 4];
+#pragma unroll
+            for (int q = 0; q < CPL / 4; ++q) dacc[q] = 0;
+            auto row = [&](auto U, int i, bool refill) {
+                constexpr int u = decltype(U)::value;
+                uint32_t Pc[CPL + 2];
+                pixels(ring[u], Pc);
+                if (refill) load_row(ring[u], rwk, vl, v0, (uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp);
+                if (t == 0) Pc[0] = Pc[1];  // left neighbour of column 0 clamped to it
+                uint32_t bits = 0;
+                if (i == 0) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
+                        S[c] = (__builtin_amdgcn_sad_u8(Pc[c], pr, 0u) << 9) | 64u;
+                        bits |= 1u << (2 * c);
+                    }
+                } else {
+                    const int b = i & 1;
+                    sm.xa[b][t] = S[0];
+                    sm.xb[b][t + 1] = S[CPL - 1];
+                    lds_barrier();
+                    const uint32_t Sl = sm.xb[b][t], Sr = sm.xa[b][t + 1];
+                    uint32_t Sn[CPL];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint32_t pl = Pc[c];
+                        const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
+                        const uint32_t cu = __builtin_amdgcn_sad_u8(pl, pr, 0u);
+                        const uint32_t sL = c == 0 ? Sl : S[c - 1];
+                        const uint32_t sR = c == CPL - 1 ? Sr : S[c + 1];
+                        uint32_t kL = (__builtin_amdgcn_sad_u8(Pup[c], pl, 0u) << 9) + sL;
+                        if (c == 0 && t == 0) kL = INF;  // column 0 has no upper-left parent
+                        const uint32_t kU = S[c] | 0x80u;
+                        const uint32_t kR = okR[c] ? ((__builtin_amdgcn_sad_u8(Pup[c], pr, 0u) << 9) + sR) | 0x100u : INF;
+                        const uint32_t kk = min(min(kL, kU), kR);
+                        const uint32_t dd = (kk >> 7) & 3u;
+                        // drop the tag, add CU to M and move the ancestor offset by dd - 1
+                        Sn[c] = kk + (cu << 9) - (127u * dd + 1u);
+                        bits |= dd << (2 * c);
+                    }
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) S[c] = Sn[c];
+                }
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) Pup[c] = Pc[c + 1];
+#pragma unroll
+                for (int q = 0; q < CPL / 4; ++q) dacc[q] |= ((bits >> (8 * q)) & 0xFFu) << (8 * (u & 3));
+                if ((u & 3) == 3 || i == H - 1) {
+#pragma unroll
+                    for (int q = 0; q < CPL / 4; ++q) {
+                        const uint32_t vo = act && j0 + 4 * q < w ? (uint32_t)(j0 / 4 + q) * 4u : kBufDrop;
+                        __builtin_amdgcn_raw_buffer_store_b32(dacc[q], rdir, (int)vo, (int)((uint32_t)(i >> 2) * gbytes), 0);
+                        dacc[q] = 0;
+                    }
+                }
+                if (i % K == K - 1 || i == H - 1) {
+                    // end of a phase: record the ancestor offsets, then restart them
+                    const int p = i / K;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        if (j0 + c < w) {
+                            if (anc_lds) sm.anc[p * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
+                            else *gp(ancg + p * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
+                        }
+                        S[c] = (S[c] & ~0x7Fu) | 64u;
+                    }
+                }
+            };
+            int i0 = 0;
+#pragma unroll 1
+            for (; i0 + PF <= H; i0 += PF) static_for<PF>([&](auto U) { row(U, i0 + decltype(U)::value, true); });
+            static_for<PF>([&](auto U) {
+                if (i0 + decltype(U)::value < H) row(U, i0 + decltype(U)::value, false);
+            });
+
+            // ---- argmin of the last row (a4): packed (M << 32 | column), the leftmost minimum
+            unsigned long long best = ~0ull;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                if (j0 + c < w) best = min(best, ((unsigned long long)(S[c] >> 9) << 32) | (unsigned)(j0 + c));
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor((long long)best, o));
+            if (lane == 0) sm.red[wv] = best;
+            __syncthreads();
+            if (t == 0) {
+                unsigned long long b = sm.red[0];
+                for (int x = 1; x < NW; ++x) b = min(b, sm.red[x]);
+                int je = (int)(b & 0xFFFFFFFFull);
+                if (d.costs_out) d.costs_out[k] = (long long)(b >> 32);
+                // ---- backtrack (a5), first hop: phase by phase through the ancestor offsets
+                sm.jend[P - 1] = je;
+                for (int p = P - 1; p > 0; --p) {
+                    const int a = anc_lds ? (int)sm.anc[p * w + je] : (int)*gp(ancg + p * w + je);
+                    je = min(max(je + a - 64, 0), w - 1);
+                    sm.jend[p - 1] = je;
+                }
+            }
+            __syncthreads();
+            // ---- then every phase's rows, one wave per phase, from an LDS window of the map
+#pragma unroll 1
+            for (int p = wv; p < P; p += NW) {
+                const int r0 = p * K, n = min(K, H - r0), ng = (n + 3) >> 2;
+                const int je = sm.jend[p];
+                const int cb0 = max(0, je - (K - 1)) >> 2;
+                uint32_t* win = sm.win[wv];
+                constexpr int NI = (GK * WD + 63) / 64;
+                uint32_t v[NI];
+                const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs) + (size_t)(r0 >> 2) * d.db;
+#pragma unroll
+                for (int m = 0; m < NI; ++m) {
+                    const int x = lane + 64 * m, g = x / WD, q = x % WD;
+                    v[m] = g < ng && cb0 + q < d.db ? *gp(src + (size_t)g * d.db + cb0 + q) : 0u;
+                }
+#pragma unroll
+                for (int m = 0; m < NI; ++m) {
+                    const int x = lane + 64 * m;
+                    if (x < GK * WD) win[x] = v[m];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                int s = je, mys = 0;
+                for (int i = n - 1; i >= 0; --i) {
+                    if (lane == i) mys = s;
+                    if (i > 0) {
+                        const int q = min(max((s >> 2) - cb0, 0), WD - 1);
+                        const uint32_t wd = win[(i >> 2) * WD + q];
+                        s += (int)((wd >> ((i & 3) * 8 + (s & 3) * 2)) & 3u) - 1;
+                        s = min(max(s, 0), w - 1);
+                    }
+                }
+                if (lane < n) {
+                    *gp(d.seam + r0 + lane) = mys;
+                    if (d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            __syncthreads();
+            // ---- removal (a6): the pixels right of the seam move one column left, two rows at a time
+#pragma unroll 1
+            for (int rc = wv * 64; rc < H; rc += NW * 64) {
+                const int n = min(64, H - rc);
+                const int sv = lane < n ? *gp(d.seam + rc + lane) : 0;
+#pragma unroll 1
+                for (int i = 0; i < n; i += 2) {
+                    const int sa = min(max(__builtin_amdgcn_readlane(sv, i), 0), w - 1);
+                    uint8_t* ra = d.wk + (long long)(rc + i) * d.wp;
+                    const SSeg a0 = sseg<false>(ra + (long long)sa * C, ra + (long long)(w - 1) * C, C);
+                    SSeg b0 = a0, none = a0;
+                    none.n = 0;
+                    b0.n = 0;
+                    if (i + 1 < n) {
+                        const int sb = min(max(__builtin_amdgcn_readlane(sv, i + 1), 0), w - 1);
+                        uint8_t* rb = d.wk + (long long)(rc + i + 1) * d.wp;
+                        b0 = sseg<false>(rb + (long long)sb * C, rb + (long long)(w - 1) * C, C);
+                    }
+                    shift_rows2_wave<2, false, false>(a0, none, b0, none, lane);
+                }
+            }
+            __syncthreads();
+        }
+        // ---- the carved rows go from wk to img
+        if (nseams > 0) {
+            const int nb = d.target_w * C;
+#pragma unroll 1
+            for (int r = wv; r < H; r += NW)
+                copy_bytes_wave(d.img + (long long)r * d.pitch, d.wk + (long long)r * d.wp, nb, lane);
+        }
+        __syncthreads();
+        if (t == 0) {
+            ctl->done = (unsigned)nseams;
+            ctl->t_end = wall_clock64();
+        }
+    }
+};
+}  // namespace fwd
+
+// One workgroup per image of `imgs`, in the order given by `order` (nullable: identity).
+template <int CPL>
+__global__ __launch_bounds__(fwd::NT, 1) void fwd_carve_kernel(const Img* __restrict__ imgs, const int* __restrict__ order,
+                                                               int n) {
+    __shared__ fwd::Smem sm;
+    if ((int)blockIdx.x >= n) return;
+    const Img d = imgs[order ? order[blockIdx.x] : blockIdx.x];
+    switch (d.C) {
+        case 1: fwd::Carver<1, CPL>::carve(d, sm); break;
+        case 2: fwd::Carver<2, CPL>::carve(d, sm); break;
+        case 3: fwd::Carver<3, CPL>::carve(d, sm); break;
+        default: fwd::Carver<4, CPL>::carve(d, sm); break;
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
 // Variant table and launchers.
 static const Variant kVariants[] = {
     {4, 32, 256, "cpl4_k32_t256"},
@@ -1294,6 +1615,12 @@ hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, uns
 #undef X
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_carve(const Img* imgs, const int* order, int n, int max_w, hipStream_t st) {
+    if (max_w <= 4096) hipLaunchKernelGGL(fwd_carve_kernel<4>, dim3(n), dim3(fwd::NT), 0, st, imgs, order, n);
+    else hipLaunchKernelGGL(fwd_carve_kernel<8>, dim3(n), dim3(fwd::NT), 0, st, imgs, order, n);
     return hipGetLastError();
 }
 

@@ -130,3 +130,30 @@ def test_tune_flag_bits_do_not_overlap():
     for f in flags:
         assert acc & f == 0
         acc |= f
+
+
+def test_forward_validation(lib):
+    assert lib.sc_forward_workspace_bytes(0, 10, 3) == 0 and lib.sc_forward_workspace_bytes(10, 10, 5) == 0
+    a = lib.sc_forward_workspace_bytes(2076, 2113, 4)
+    assert a % 256 == 0 and a > 2076 * 2113 * 4  # the working copy alone
+    ws = ctypes.c_void_p(1 << 40)
+    # width beyond the forward path, cost bound, bad target, small or misaligned workspace
+    assert lib.sc_carve_forward(None, FAKE, 4, 8193, 1, 8193, 8000, None, None, ws, 1 << 30,
+                                None) == _lib.SC_EUNSUPPORTED
+    assert lib.sc_carve_forward(None, FAKE, 5483, 5, 3, 15, 4, None, None, ws, 1 << 30, None) == _lib.SC_EUNSUPPORTED
+    assert lib.sc_carve_forward(None, FAKE, 4, 8, 3, 24, 0, None, None, ws, 1 << 20, None) == _lib.SC_EINVAL
+    assert lib.sc_carve_forward(None, FAKE, 4, 8, 3, 24, 9, None, None, ws, 1 << 20, None) == _lib.SC_EINVAL
+    assert lib.sc_carve_forward(None, FAKE, 4, 8, 3, 24, 4, None, None, ws, 64, None) == _lib.SC_ENOMEM
+    assert lib.sc_carve_forward(None, FAKE, 4, 8, 3, 24, 4, None, None, ctypes.c_void_p((1 << 40) + 8), 1 << 20,
+                                None) == _lib.SC_EINVAL
+    jobs = (_lib.sc_job * 2)()
+    jobs[0] = _lib.sc_job(None, 0x1000, 4, 8, 3, 24, 4, None, None)
+    jobs[1] = _lib.sc_job(None, 0x2000, 5, 9000, 1, 9000, 10, None, None)
+    info = _lib.sc_batch_info()
+    assert lib.sc_forward_batch_prepare(jobs, 2, ws, 1 << 40, ctypes.byref(info)) == _lib.SC_EUNSUPPORTED
+    assert lib.sc_forward_batch_prepare(jobs, 1, ws, 64, ctypes.byref(info)) == _lib.SC_ENOMEM
+    # an e1 batch plan is not a forward plan and the other way round
+    info.n, info.nblocks, info.team, info.variant = 1, 1, 4, 7
+    assert lib.sc_forward_batch_launch(ctypes.byref(info), ws, None) == _lib.SC_EINVAL
+    info.team, info.variant = 0, 100
+    assert lib.sc_batch_launch(ctypes.byref(info), ws, None) == _lib.SC_EINVAL
