@@ -540,6 +540,7 @@ def forward(args, dev):
     t_first = min(tb for tb, _ in times)
     lat_ms = [(te - t_first) * 1000.0 for _, te in times]
     longest = int(np.argmax([te - tb for tb, te in times]))
+    stages = fb.stages()
     model_bytes = sum(forward_byte_model(j.h, j.w, 3, j.seams) for j in jobs)
     achieved = model_bytes / (carve_ms / 1000.0) / 1e9
     out = {
@@ -556,7 +557,10 @@ def forward(args, dev):
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
                        "max": round(max(lat_ms), 2)},
         "longest_image": {"h": jobs[longest].h, "w": jobs[longest].w, "seams": jobs[longest].seams,
-                          "run_ms": round((times[longest][1] - times[longest][0]) * 1000.0, 1)},
+                          "run_ms": round((times[longest][1] - times[longest][0]) * 1000.0, 1),
+                          "dp_ms": round(float(stages[longest][0]) * 1e3, 1),
+                          "backtrack_ms": round(float(stages[longest][1]) * 1e3, 1),
+                          "removal_ms": round(float(stages[longest][2]) * 1e3, 1)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, fb.results(), args.cpu_seconds, forward=True)

@@ -388,5 +388,9 @@ class ForwardBatch:
         """Per-image (begin, end) of the last carve in seconds of the device clock."""
         return read_times(self.ws, len(self.jobs))
 
+    def stages(self):
+        """Per-image seconds in (DP sweep, argmin + backtrack, removal) of the last carve."""
+        return read_stages(self.ws, len(self.jobs))
+
     def results(self):
         return [(j.img[:, : j.target_w], j.seams, j.costs) for j in self.jobs]

@@ -1289,6 +1289,21 @@ struct Smem {
     uint8_t anc[ANC_LDS];
 };
 
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t o;
+    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(o) : "v"(a), "v"(b), "v"(c));
+    return o;
+}
+
+// kk + (cu << 9) - 127 * tag - 1 with tag = bits 7-8 of kk: drops the tag, adds CU to M and moves
+// the ancestor offset by tag - 1.
+__device__ __forceinline__ uint32_t next_state(uint32_t kk, uint32_t cu) {
+    const uint32_t tag = (kk >> 7) & 3u;
+    uint32_t o;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(o) : "v"(tag), "s"(-127), "v"(kk + (cu << 9) - 1u));
+    return o;
+}
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -1339,6 +1354,7 @@ struct Carver {
         int w = d.W;
 #pragma unroll 1
         for (int k = 0; k < nseams; ++k, --w) {
+            const unsigned long long tm0 = t == 0 ? wall_clock64() : 0ull;
             const bool act = j0 < w;
             // per-lane byte offsets of column j0 and of the dword left of it in a row; dropped for
             // idle threads and left of column 0 (that neighbour is clamped to column 0 below)
@@ -1366,69 +1382,80 @@ struct Carver {
             uint32_t S[CPL], Pup[CPL], dacc[CPL / 4];
 #pragma unroll
             for (int q = 0; q < CPL / 4; ++q) dacc[q] = 0;
+            // Threads whose columns all lie beyond the current width only take part in the row
+            // barrier and issue their (dropped) prefetch loads; a wave of them skips the arithmetic.
             auto row = [&](auto U, int i, bool refill) {
                 constexpr int u = decltype(U)::value;
                 uint32_t Pc[CPL + 2];
-                pixels(ring[u], Pc);
+                if (act) pixels(ring[u], Pc);
                 if (refill) load_row(ring[u], rwk, vl, v0, (uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp);
-                if (t == 0) Pc[0] = Pc[1];  // left neighbour of column 0 clamped to it
-                uint32_t bits = 0;
-                if (i == 0) {
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
-                        S[c] = (__builtin_amdgcn_sad_u8(Pc[c], pr, 0u) << 9) | 64u;
-                        bits |= 1u << (2 * c);
-                    }
-                } else {
+                uint32_t Sl = 0, Sr = 0;
+                if (i > 0) {
                     const int b = i & 1;
-                    sm.xa[b][t] = S[0];
-                    sm.xb[b][t + 1] = S[CPL - 1];
+                    if (act) {
+                        sm.xa[b][t] = S[0];
+                        sm.xb[b][t + 1] = S[CPL - 1];
+                    }
                     lds_barrier();
-                    const uint32_t Sl = sm.xb[b][t], Sr = sm.xa[b][t + 1];
-                    uint32_t Sn[CPL];
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const uint32_t pl = Pc[c];
-                        const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
-                        const uint32_t cu = __builtin_amdgcn_sad_u8(pl, pr, 0u);
-                        const uint32_t sL = c == 0 ? Sl : S[c - 1];
-                        const uint32_t sR = c == CPL - 1 ? Sr : S[c + 1];
-                        uint32_t kL = (__builtin_amdgcn_sad_u8(Pup[c], pl, 0u) << 9) + sL;
-                        if (c == 0 && t == 0) kL = INF;  // column 0 has no upper-left parent
-                        const uint32_t kU = S[c] | 0x80u;
-                        const uint32_t kR = okR[c] ? ((__builtin_amdgcn_sad_u8(Pup[c], pr, 0u) << 9) + sR) | 0x100u : INF;
-                        const uint32_t kk = min(min(kL, kU), kR);
-                        const uint32_t dd = (kk >> 7) & 3u;
-                        // drop the tag, add CU to M and move the ancestor offset by dd - 1
-                        Sn[c] = kk + (cu << 9) - (127u * dd + 1u);
-                        bits |= dd << (2 * c);
-                    }
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) S[c] = Sn[c];
-                }
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) Pup[c] = Pc[c + 1];
-#pragma unroll
-                for (int q = 0; q < CPL / 4; ++q) dacc[q] |= ((bits >> (8 * q)) & 0xFFu) << (8 * (u & 3));
-                if ((u & 3) == 3 || i == H - 1) {
-#pragma unroll
-                    for (int q = 0; q < CPL / 4; ++q) {
-                        const uint32_t vo = act && j0 + 4 * q < w ? (uint32_t)(j0 / 4 + q) * 4u : kBufDrop;
-                        __builtin_amdgcn_raw_buffer_store_b32(dacc[q], rdir, (int)vo, (int)((uint32_t)(i >> 2) * gbytes), 0);
-                        dacc[q] = 0;
+                    if (act) {
+                        Sl = sm.xb[b][t];
+                        Sr = sm.xa[b][t + 1];
                     }
                 }
-                if (i % K == K - 1 || i == H - 1) {
-                    // end of a phase: record the ancestor offsets, then restart them
-                    const int p = i / K;
+                if (act) {
+                    if (t == 0) Pc[0] = Pc[1];  // left neighbour of column 0 clamped to it
+                    uint32_t bits = 0;
+                    if (i == 0) {
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        if (j0 + c < w) {
-                            if (anc_lds) sm.anc[p * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
-                            else *gp(ancg + p * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
+                        for (int c = 0; c < CPL; ++c) {
+                            const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
+                            S[c] = (__builtin_amdgcn_sad_u8(Pc[c], pr, 0u) << 9) | 64u;
+                            bits |= 1u << (2 * c);
                         }
-                        S[c] = (S[c] & ~0x7Fu) | 64u;
+                    } else {
+                        uint32_t Sn[CPL];
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) {
+                            const uint32_t pl = Pc[c];
+                            const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
+                            const uint32_t cu = __builtin_amdgcn_sad_u8(pl, pr, 0u);
+                            const uint32_t sL = c == 0 ? Sl : S[c - 1];
+                            const uint32_t sR = c == CPL - 1 ? Sr : S[c + 1];
+                            uint32_t kL = (__builtin_amdgcn_sad_u8(Pup[c], pl, 0u) << 9) + sL;
+                            if (c == 0 && t == 0) kL = INF;  // column 0 has no upper-left parent
+                            const uint32_t kU = S[c] | 0x80u;
+                            const uint32_t kR =
+                                okR[c] ? ((__builtin_amdgcn_sad_u8(Pup[c], pr, 0u) << 9) + sR) | 0x100u : INF;
+                            const uint32_t kk = min3u(kL, kU, kR);
+                            Sn[c] = next_state(kk, cu);
+                            bits |= ((kk >> 7) & 3u) << (2 * c);
+                        }
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) S[c] = Sn[c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) Pup[c] = Pc[c + 1];
+#pragma unroll
+                    for (int q = 0; q < CPL / 4; ++q) dacc[q] |= ((bits >> (8 * q)) & 0xFFu) << (8 * (u & 3));
+                    if ((u & 3) == 3 || i == H - 1) {
+#pragma unroll
+                        for (int q = 0; q < CPL / 4; ++q) {
+                            const uint32_t vo = j0 + 4 * q < w ? (uint32_t)(j0 / 4 + q) * 4u : kBufDrop;
+                            __builtin_amdgcn_raw_buffer_store_b32(dacc[q], rdir, (int)vo, (int)((uint32_t)(i >> 2) * gbytes), 0);
+                            dacc[q] = 0;
+                        }
+                    }
+                    if (i % K == K - 1 || i == H - 1) {
+                        // end of a phase: record the ancestor offsets, then restart them
+                        const int p = i / K;
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) {
+                            if (j0 + c < w) {
+                                if (anc_lds) sm.anc[p * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
+                                else *gp(ancg + p * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
+                            }
+                            S[c] = (S[c] & ~0x7Fu) | 64u;
+                        }
                     }
                 }
             };
@@ -1448,6 +1475,7 @@ struct Carver {
             for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor((long long)best, o));
             if (lane == 0) sm.red[wv] = best;
             __syncthreads();
+            const unsigned long long tm1 = t == 0 ? wall_clock64() : 0ull;
             if (t == 0) {
                 unsigned long long b = sm.red[0];
                 for (int x = 1; x < NW; ++x) b = min(b, sm.red[x]);
@@ -1504,28 +1532,34 @@ struct Carver {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             __syncthreads();
-            // ---- removal (a6): the pixels right of the seam move one column left, two rows at a time
+            const unsigned long long tm2 = t == 0 ? wall_clock64() : 0ull;
+            // ---- removal (a6): the pixels right of the seam move one column left, four rows per
+            // memory round trip (the shifter's four segments are four rows here)
 #pragma unroll 1
             for (int rc = wv * 64; rc < H; rc += NW * 64) {
                 const int n = min(64, H - rc);
                 const int sv = lane < n ? *gp(d.seam + rc + lane) : 0;
-#pragma unroll 1
-                for (int i = 0; i < n; i += 2) {
-                    const int sa = min(max(__builtin_amdgcn_readlane(sv, i), 0), w - 1);
-                    uint8_t* ra = d.wk + (long long)(rc + i) * d.wp;
-                    const SSeg a0 = sseg<false>(ra + (long long)sa * C, ra + (long long)(w - 1) * C, C);
-                    SSeg b0 = a0, none = a0;
-                    none.n = 0;
-                    b0.n = 0;
-                    if (i + 1 < n) {
-                        const int sb = min(max(__builtin_amdgcn_readlane(sv, i + 1), 0), w - 1);
-                        uint8_t* rb = d.wk + (long long)(rc + i + 1) * d.wp;
-                        b0 = sseg<false>(rb + (long long)sb * C, rb + (long long)(w - 1) * C, C);
+                auto seg = [&](int i) {
+                    if (i >= n) {
+                        SSeg g;
+                        g.base = d.wk;
+                        g.q0 = g.q1 = g.sh = g.n = 0;
+                        return g;
                     }
-                    shift_rows2_wave<2, false, false>(a0, none, b0, none, lane);
-                }
+                    const int si = min(max(__builtin_amdgcn_readlane(sv, i), 0), w - 1);
+                    uint8_t* r = d.wk + (long long)(rc + i) * d.wp;
+                    return sseg<false>(r + (long long)si * C, r + (long long)(w - 1) * C, C);
+                };
+#pragma unroll 1
+                for (int i = 0; i < n; i += 4) shift_rows2_wave<2, false, false>(seg(i), seg(i + 1), seg(i + 2), seg(i + 3), lane);
             }
             __syncthreads();
+            if (t == 0) {  // device clock per stage: DP sweep; argmin + backtrack; removal
+                const unsigned long long tm3 = wall_clock64();
+                ctl->t_stage[0] += tm1 - tm0;
+                ctl->t_stage[1] += tm2 - tm1;
+                ctl->t_stage[2] += tm3 - tm2;
+            }
         }
         // ---- the carved rows go from wk to img
         if (nseams > 0) {
