@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "pixel-seams removed/sec + HBM GB/s %peak; p50/p99 carve latency, batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "carve_batch_c4_traffic.json")
+FWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_carve_batch_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_21207_amd", "csrc", f)
                   for f in ("sc_kernels.hip", "sc_internal.h")]
 
@@ -542,6 +543,12 @@ def forward(args, dev):
     longest = int(np.argmax([te - tb for tb, te in times]))
     stages = fb.stages()
     model_bytes = sum(forward_byte_model(j.h, j.w, 3, j.seams) for j in jobs)
+    fwd_traffic = None
+    if os.path.exists(FWD_TRAFFIC_FILE):
+        with open(FWD_TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash():
+            fwd_traffic = tr.get("bytes_per_launch")
     achieved = model_bytes / (carve_ms / 1000.0) / 1e9
     out = {
         "metric": METRIC, "value": round(pixel_seams / (ms_per_step / 1000.0), 1), "unit": "pixel-seams/s",
@@ -551,7 +558,7 @@ def forward(args, dev):
                                "H,W~U[240,2160], 10-40% of width removed (seed 3)",
                    "images": len(jobs), "pixel_seams": pixel_seams},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "fwd_carve_kernel",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": fwd_traffic, "kernel": "fwd_carve_kernel",
                      "model_bytes_per_launch": model_bytes, "kernel_ms": round(carve_ms, 3)},
         "copy_pass_ms": round(copy_ms, 3),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
