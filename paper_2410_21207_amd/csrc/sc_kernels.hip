@@ -1370,42 +1370,38 @@ struct Carver {
             for (int c = 0; c < CPL; ++c) okR[c] = j0 + c + 1 < w;
 
             // ---- DP over the rows (a3 with forward costs)
+            // The compute unit's scalar unit is shared by all 16 waves, so the row loop keeps its
+            // scalar work small: a wave with no column in range only joins the H-1 row barriers,
+            // the others run with no per-lane branches (idle lanes of the boundary wave compute
+            // values nobody reads; their loads and stores are dropped), row 0 and the last row
+            // are tested only where they can occur, and phases end on a scalar countdown.
             // Rows go in blocks of PF with the ring slot of a row refilled right after its pixels
             // are taken.  The refills of full blocks are unconditional (clamped to the last row),
             // so no ring register is merged across a branch: a merge would need a copy of a
             // register whose load is still in flight, i.e. a wait for every outstanding load.
-            uint32_t ring[PF][NDW];
-            static_for<PF>([&](auto U) {
-                constexpr int u = decltype(U)::value;
-                load_row(ring[u], rwk, vl, v0, (uint32_t)min(u, H - 1) * (uint32_t)d.wp);
-            });
-            uint32_t S[CPL], Pup[CPL], dacc[CPL / 4];
+            uint32_t S[CPL];
+            if (wv * 64 * CPL >= w) {
+#pragma unroll 1
+                for (int i = 1; i < H; ++i) lds_barrier();
+            } else {
+                uint32_t ring[PF][NDW];
+                static_for<PF>([&](auto U) {
+                    constexpr int u = decltype(U)::value;
+                    load_row(ring[u], rwk, vl, v0, (uint32_t)min(u, H - 1) * (uint32_t)d.wp);
+                });
+                uint32_t Pup[CPL], dacc[CPL / 4];
 #pragma unroll
-            for (int q = 0; q < CPL / 4; ++q) dacc[q] = 0;
-            // Threads whose columns all lie beyond the current width only take part in the row
-            // barrier and issue their (dropped) prefetch loads; a wave of them skips the arithmetic.
-            auto row = [&](auto U, int i, bool refill) {
-                constexpr int u = decltype(U)::value;
-                uint32_t Pc[CPL + 2];
-                if (act) pixels(ring[u], Pc);
-                if (refill) load_row(ring[u], rwk, vl, v0, (uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp);
-                uint32_t Sl = 0, Sr = 0;
-                if (i > 0) {
-                    const int b = i & 1;
-                    if (act) {
-                        sm.xa[b][t] = S[0];
-                        sm.xb[b][t + 1] = S[CPL - 1];
-                    }
-                    lds_barrier();
-                    if (act) {
-                        Sl = sm.xb[b][t];
-                        Sr = sm.xa[b][t + 1];
-                    }
-                }
-                if (act) {
+                for (int q = 0; q < CPL / 4; ++q) dacc[q] = 0;
+                int kleft = K, phase = 0;  // rows left in the current phase; its index
+                auto row = [&](auto U, int i, auto LAST) {
+                    constexpr int u = decltype(U)::value;
+                    constexpr bool last = decltype(LAST)::value;  // the block holds row H-1: no refill
+                    uint32_t Pc[CPL + 2];
+                    pixels(ring[u], Pc);
+                    if (!last) load_row(ring[u], rwk, vl, v0, (uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp);
                     if (t == 0) Pc[0] = Pc[1];  // left neighbour of column 0 clamped to it
                     uint32_t bits = 0;
-                    if (i == 0) {
+                    if (u == 0 && i == 0) {
 #pragma unroll
                         for (int c = 0; c < CPL; ++c) {
                             const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
@@ -1413,6 +1409,11 @@ struct Carver {
                             bits |= 1u << (2 * c);
                         }
                     } else {
+                        const int b = i & 1;
+                        sm.xa[b][t] = S[0];
+                        sm.xb[b][t + 1] = S[CPL - 1];
+                        lds_barrier();
+                        const uint32_t Sl = sm.xb[b][t], Sr = sm.xa[b][t + 1];
                         uint32_t Sn[CPL];
 #pragma unroll
                         for (int c = 0; c < CPL; ++c) {
@@ -1437,7 +1438,7 @@ struct Carver {
                     for (int c = 0; c < CPL; ++c) Pup[c] = Pc[c + 1];
 #pragma unroll
                     for (int q = 0; q < CPL / 4; ++q) dacc[q] |= ((bits >> (8 * q)) & 0xFFu) << (8 * (u & 3));
-                    if ((u & 3) == 3 || i == H - 1) {
+                    if ((u & 3) == 3 || (last && i == H - 1)) {
 #pragma unroll
                         for (int q = 0; q < CPL / 4; ++q) {
                             const uint32_t vo = j0 + 4 * q < w ? (uint32_t)(j0 / 4 + q) * 4u : kBufDrop;
@@ -1445,26 +1446,28 @@ struct Carver {
                             dacc[q] = 0;
                         }
                     }
-                    if (i % K == K - 1 || i == H - 1) {
+                    if (--kleft == 0 || (last && i == H - 1)) {
                         // end of a phase: record the ancestor offsets, then restart them
-                        const int p = i / K;
 #pragma unroll
                         for (int c = 0; c < CPL; ++c) {
                             if (j0 + c < w) {
-                                if (anc_lds) sm.anc[p * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
-                                else *gp(ancg + p * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
+                                if (anc_lds) sm.anc[phase * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
+                                else *gp(ancg + phase * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
                             }
                             S[c] = (S[c] & ~0x7Fu) | 64u;
                         }
+                        kleft = K;
+                        ++phase;
                     }
-                }
-            };
-            int i0 = 0;
+                };
+                int i0 = 0;
 #pragma unroll 1
-            for (; i0 + PF <= H; i0 += PF) static_for<PF>([&](auto U) { row(U, i0 + decltype(U)::value, true); });
-            static_for<PF>([&](auto U) {
-                if (i0 + decltype(U)::value < H) row(U, i0 + decltype(U)::value, false);
-            });
+                for (; i0 + PF < H; i0 += PF)
+                    static_for<PF>([&](auto U) { row(U, i0 + decltype(U)::value, std::false_type{}); });
+                static_for<PF>([&](auto U) {
+                    if (i0 + decltype(U)::value < H) row(U, i0 + decltype(U)::value, std::true_type{});
+                });
+            }
 
             // ---- argmin of the last row (a4): packed (M << 32 | column), the leftmost minimum
             unsigned long long best = ~0ull;
