@@ -1537,11 +1537,12 @@ struct Carver {
             __syncthreads();
             const unsigned long long tm2 = t == 0 ? wall_clock64() : 0ull;
             // ---- removal (a6): the pixels right of the seam move one column left, four rows per
-            // memory round trip (the shifter's four segments are four rows here)
+            // memory round trip (the shifter's four segments are four rows here); the 4-row groups
+            // are dealt to the waves round-robin so every wave moves about the same number of rows
 #pragma unroll 1
-            for (int rc = wv * 64; rc < H; rc += NW * 64) {
-                const int n = min(64, H - rc);
-                const int sv = lane < n ? *gp(d.seam + rc + lane) : 0;
+            for (int r0 = wv * 4; r0 < H; r0 += NW * 4) {
+                const int n = min(4, H - r0);
+                const int sv = lane < n ? *gp(d.seam + r0 + lane) : 0;
                 auto seg = [&](int i) {
                     if (i >= n) {
                         SSeg g;
@@ -1550,11 +1551,10 @@ struct Carver {
                         return g;
                     }
                     const int si = min(max(__builtin_amdgcn_readlane(sv, i), 0), w - 1);
-                    uint8_t* r = d.wk + (long long)(rc + i) * d.wp;
+                    uint8_t* r = d.wk + (long long)(r0 + i) * d.wp;
                     return sseg<false>(r + (long long)si * C, r + (long long)(w - 1) * C, C);
                 };
-#pragma unroll 1
-                for (int i = 0; i < n; i += 4) shift_rows2_wave<2, false, false>(seg(i), seg(i + 1), seg(i + 2), seg(i + 3), lane);
+                shift_rows2_wave<2, false, false>(seg(0), seg(1), seg(2), seg(3), lane);
             }
             __syncthreads();
             if (t == 0) {  // device clock per stage: DP sweep; argmin + backtrack; removal
