@@ -1238,6 +1238,16 @@ __global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint
     }
 }
 
+// Calls f(std::integral_constant<int, 0>{}) ... f(std::integral_constant<int, N-1>{}) in order.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
 // ----------------------------------------------------------------------------------------------
 // Forward energy (sec. "Forward Energy Calculation", the standard definition with no per-pixel
 // term): the DP cost of removing pixel (i,j) is the difference of the pixel pairs its removal
@@ -1258,15 +1268,6 @@ __global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint
 // (to the workspace when they do not fit), so the backtrack hops phase by phase and then walks
 // the K rows of every phase in parallel from an LDS window of the 2-bit direction map.  Removal
 // moves the pixels right of the seam one column left with the in-place slot shifter.
-// Calls f(std::integral_constant<int, 0>{}) ... f(std::integral_constant<int, N-1>{}) in order.
-template <class F, int... I>
-__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    static_for_seq(f, std::make_integer_sequence<int, N>{});
-}
 
 namespace fwd {
 constexpr int NT = 1024;
@@ -1370,11 +1371,11 @@ struct Carver {
             for (int c = 0; c < CPL; ++c) okR[c] = j0 + c + 1 < w;
 
             // ---- DP over the rows (a3 with forward costs)
-            // The compute unit's scalar unit is shared by all 16 waves, so the row loop keeps its
-            // scalar work small: a wave with no column in range only joins the H-1 row barriers,
-            // the others run with no per-lane branches (idle lanes of the boundary wave compute
-            // values nobody reads; their loads and stores are dropped), row 0 and the last row
-            // are tested only where they can occur, and phases end on a scalar countdown.
+            // The row loop keeps its per-row overhead small: a wave with no column in range only
+            // joins the H-1 row barriers, the others run with no per-lane branches (idle lanes of
+            // the boundary wave compute values nobody reads; their loads and stores are dropped),
+            // row 0 and the last row are tested only where they can occur, and phases end on a
+            // scalar countdown.
             // Rows go in blocks of PF with the ring slot of a row refilled right after its pixels
             // are taken.  The refills of full blocks are unconditional (clamped to the last row),
             // so no ring register is merged across a branch: a merge would need a copy of a
