@@ -103,7 +103,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward"], default="batch",
+    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward", "forward1080p"],
+                    default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
                          "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal); "
                          "insert: 1920x1080 widened by 480 seams; sweep: the paper's size sweep of square "
@@ -134,6 +135,9 @@ def main():
         return
     if args.workload == "forward":
         forward(args, dev)
+        return
+    if args.workload == "forward1080p":
+        forward_single(args, dev)
         return
     if args.workload != "batch":
         single(args, dev)
@@ -572,6 +576,39 @@ def forward(args, dev):
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, fb.results(), args.cpu_seconds, forward=True)
     print(json.dumps(out), flush=True)
+
+
+def forward_single(args, dev):
+    """Forward-energy carve of one 1920x1080 RGB image to 1440 columns (480 seams)."""
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    H, W, tw = 1080, 1920, 1440
+    src = torch.from_numpy(synth.blob_image(H, W, 3, seed=1)).to(dev)
+    dst = torch.empty_like(src)
+    ws = api.workspace(api._lib.load().sc_forward_workspace_bytes(H, W, 3), dev)
+    ps = H * sum(range(tw + 1, W + 1))
+    for _ in range(args.warmup):
+        api.carve_forward(dst, tw, src=src, record=False, ws=ws)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        api.carve_forward(dst, tw, src=src, record=False, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": METRIC, "value": round(ps / wall, 1), "unit": "pixel-seams/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1000.0, 3),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                      "data": "synthetic",
+                      "config": {"workload": "forward-energy carve: one 1920x1080 RGB uint8 blob+noise image "
+                                             "(seed 1) to 1440 columns", "pixel_seams": ps},
+                      "gpu_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 3)}), flush=True)
 
 
 def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False):
