@@ -94,15 +94,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--team", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
-    ap.add_argument("--no-prio", action="store_true",
-                    help="run every image at the same wave priority")
     ap.add_argument("--no-minside", action="store_true",
                     help="remove every seam pixel by shifting the right part (no min-side removal)")
     ap.add_argument("--n", type=int, default=256, help="images in the batch (256 = the configuration)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-sample", type=int, default=24)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU oracle sample: about this many seconds of work per host core (the batch's "
+                         "critical image is always in the sample)")
     ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward", "forward1080p"],
                     default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
@@ -154,8 +154,7 @@ def main():
     torch.cuda.synchronize()
 
     minside = not args.no_minside
-    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant, minside=minside,
-                         prio=not args.no_prio)
+    bc = api.BatchCarver(dsts, targets, srcs=srcs, team=args.team, variant=args.variant, minside=minside)
     stream = torch.cuda.current_stream()
 
     def step(evs=None):
@@ -183,6 +182,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_per_step = wall * 1000.0 / args.steps
+    status = bc.status()  # a device failure during the timed steps voids the measurement
+    assert all(s == 0 for s in status), f"device status after the timed steps {status}"
     energy_ms = [e[0].elapsed_time(e[1]) for e in events]
     carve_ms = [e[1].elapsed_time(e[2]) for e in events]
     log(f"steps: {ms_per_step:.1f} ms/step; energy pass {np.mean(energy_ms):.2f} ms; carve {np.mean(carve_ms):.1f} ms")
@@ -235,8 +236,7 @@ def main():
                                "10-40% of width removed (seed 3)",
                    "images": len(jobs), "seams": seams_total, "pixel_seams": pixel_seams,
                    "team": bc.info.team, "variant": api.variants()[bc.info.variant], "minside": minside,
-                   "prio": not args.no_prio, "autotuned": args.team is None and args.variant is None
-                   and bc.tuned != (None, None)},
+                   "autotuned": args.team is None and args.variant is None and bc.tuned != (None, None)},
         "roofline": roofline,
         "hbm_gbps_step": round(model_bytes / (ms_per_step / 1000.0) / 1e9, 1),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
@@ -250,10 +250,11 @@ def main():
                           "dp_ms": round(float(stages[longest, 0]) * 1e3, 1),
                           "backtrack_removal_ms": round(float(stages[longest, 1]) * 1e3, 1),
                           "band_ms": round(float(stages[longest, 2]) * 1e3, 1)},
-        "teams": bc.info.pad0,
+        "teams": bc.info.teams_used,
     }
 
     # graph replay of the same launch (informative)
+    replayed = False
     try:
         bc.capture()
         torch.cuda.synchronize()
@@ -261,8 +262,12 @@ def main():
         bc.replay()
         torch.cuda.synchronize()
         out["graph_replay_ms"] = round((time.perf_counter() - tg) * 1000.0, 3)
+        replayed = True
     except Exception as ex:  # pragma: no cover - informative only
         out["graph_replay_ms"] = f"unavailable: {ex}"
+    if replayed:
+        status = bc.status()
+        assert all(s == 0 for s in status), f"device status after the graph replay {status}"
 
     if not args.no_plain:
         # plain path: sequential sc_carve calls on one stream over a seeded sample of the images
@@ -285,8 +290,14 @@ def main():
                         "batched_speedup": round((pixel_seams / (ms_per_step / 1000.0)) / (ps / tp), 2)}
         log(f"plain: {out['plain']}")
 
+    copy = copy_bandwidth(dev)
+    out["roofline"]["copy_gbps"] = copy
+    out["roofline"]["frac_of_copy"] = round(achieved / copy, 4)
+    log(f"copy probe: {copy} GB/s")
+
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, res, args.cpu_seconds)
+        heaviest = int(np.argmax([j.pixel_seams for j in jobs]))
+        out["cpu_baseline"] = cpu_baseline(jobs, imgs_np, res, args.cpu_seconds, must=(longest, heaviest))
     print(json.dumps(out), flush=True)
 
 
@@ -611,8 +622,12 @@ def forward_single(args, dev):
                       "gpu_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 3)}), flush=True)
 
 
-def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False):
-    """The oracle, as it stands, on a bounded sample of the same workload on the host cores."""
+def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False, must=()):
+    """The oracle, as it stands, on a bounded sample of the same workload on the host cores.
+
+    The sample is the images in `must` (the batch's critical images), then images in job order up
+    to about `seconds` of work per core; every sampled image's seams, costs and output pixels are
+    compared with the GPU's."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
@@ -622,11 +637,13 @@ def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False):
     except AttributeError:  # pragma: no cover
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    # sample: the images in job order, up to ~seconds of work per core at the oracle's usual rate
     budget = seconds * (3e7 if forward else 1e8) * cores  # the forward oracle does three pair sums per cell
-    idx, acc = [], 0
+    idx = list(dict.fromkeys(int(i) for i in must))
+    acc = sum(jobs[i].pixel_seams for i in idx)
     for i, j in enumerate(jobs):
-        if acc + j.pixel_seams > budget and idx:
+        if i in idx:
+            continue
+        if acc + j.pixel_seams > budget:
             continue
         idx.append(i)
         acc += j.pixel_seams
@@ -641,13 +658,45 @@ def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False):
 
     t = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
-        outs = list(ex.map(run, idx))
+        outs = list(ex.map(run, idx))  # the critical images start first
     dt = time.perf_counter() - t
-    agree = all(np.array_equal(o[1], gpu_results[i][1].cpu().numpy()) for o, i in zip(outs, idx))
+    agree = {"seams": True, "costs": True, "pixels": True}
+    for o, i in zip(outs, idx):
+        g_out, g_seams, g_costs = gpu_results[i]
+        if g_seams is None:
+            agree["seams"] &= o[1].size == 0
+            agree["costs"] &= o[2].size == 0
+        else:
+            agree["seams"] &= bool(np.array_equal(o[1], g_seams.cpu().numpy()))
+            agree["costs"] &= bool(np.array_equal(o[2], g_costs.cpu().numpy()))
+        agree["pixels"] &= bool(np.array_equal(o[0], g_out.cpu().numpy()))
+    crit = ", ".join(f"{jobs[i].w}x{jobs[i].h}" for i in dict.fromkeys(int(i) for i in must))
     return {"value": round(acc / dt, 1), "unit": "pixel-seams/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} of the {len(jobs)} batch images (job order, ~{seconds:.0f}s per core), "
-                      f"full carves, one image per thread, {dt:.1f}s wall",
-            "seams_match_gpu": bool(agree)}
+            "sample": f"{len(idx)} of the {len(jobs)} batch images (the critical image(s) {crit}, then job "
+                      f"order up to ~{seconds:.0f}s per core), full carves, one image per thread, {dt:.1f}s wall",
+            "seams_match_gpu": agree["seams"], "costs_match_gpu": agree["costs"],
+            "pixels_match_gpu": agree["pixels"]}
+
+
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes, timed with HIP events on
+    its stream; read plus write bytes per second."""
+    import torch
+
+    a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    torch.cuda.synchronize()
+    gbps = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
 
 
 if __name__ == "__main__":

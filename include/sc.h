@@ -28,7 +28,12 @@
  *     must fit 23 bits); W <= 65535.  Violations return SC_EUNSUPPORTED.
  *   - Errors are negative return codes; sc_last_error() gives the text.  No
  *     C++ exception crosses the ABI.  Device-side failures (a team barrier
- *     that timed out) are reported through sc_read_status().
+ *     that timed out, a team not placed on one XCD) are reported through
+ *     sc_read_status(): the image's results are then invalid.
+ *   - Argument order: the arguments of the problem statement (image, its
+ *     shape, the target, outputs, workspace, stream) come first; optional
+ *     launch plumbing (a source image, a launch shape, extra outputs) trails,
+ *     nullable.
  *   - Thread safety: calls are reentrant; calls that share a workspace must be
  *     ordered on one stream.
  */
@@ -79,12 +84,13 @@ sc_status sc_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t*
  *              (no fault).
  *   seam     : H int32, written.
  *   cost     : 1 int64, written (sum of e along the seam).
- *   dirs_out : nullable; H*W uint8 receives the parent direction of every
- *              cell (0 = upper-left, 1 = up, 2 = upper-right; row 0 is 1).
  *   ws       : workspace of at least sc_workspace_bytes(H, W, 1) bytes.
+ * Trailing argument (nullable):
+ *   dirs_out : H*W uint8 receives the parent direction of every cell
+ *              (0 = upper-left, 1 = up, 2 = upper-right; row 0 is 1).
  */
-sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, uint8_t* dirs_out,
-                     void* ws, size_t ws_bytes, void* stream);
+sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, void* ws, size_t ws_bytes,
+                     void* stream, uint8_t* dirs_out);
 
 /*
  * Remove one vertical seam (sec. "Removal of Seams"): in row i the pixels
@@ -113,9 +119,6 @@ typedef struct {
 /* Remove every seam pixel by moving the pixels right of it (the paper's removal literally)
  * instead of moving whichever side of the row is shorter.  Results are identical. */
 #define SC_TUNE_NO_MINSIDE 1
-/* Batches: run every image at the same wave priority (by default the images with the longest
- * seams-by-rows chains run at a raised priority on their SIMDs).  Results are identical. */
-#define SC_TUNE_NO_PRIO 2
 /* sc_carve (and the carve inside sc_insert_seams): bits 8..10 of flags name the XCD (0..7) the
  * team's workgroups run on, so that concurrent carves on different streams can use different
  * XCDs.  Default 0.  Results are identical. */
@@ -129,21 +132,26 @@ const char* sc_variant_name(int v);
 /*
  * Carve one image to target_w columns by removing W-target_w vertical seams
  * one at a time (the flowchart loop of the paper; each seam is the minimum
- * seam of the current image).  One persistent kernel runs the whole loop on
- * the device.
- *   src       : nullable.  When given, the H x W x C image is read from src
- *               (pitch `pitch`) and written to img before carving; else img is
- *               carved in place.
+ * seam of the current image, Alg. 3 Require/Ensure: an n x m image in, an
+ * n x m' image out).  One persistent kernel runs the whole loop on the device.
  *   img       : the image; on return the first target_w*C bytes of each row
  *               hold the result (pitch unchanged).
+ *   target_w  : 1 <= target_w <= W; target_w == W copies src (if given) and
+ *               removes nothing.
+ *   pitch     : bytes per row of img (and of src), >= W*C.
  *   seams_out : nullable, (W-target_w)*H int32; seam k at seams_out[k*H + i].
  *   costs_out : nullable, (W-target_w) int64.
- *   tune      : host pointer, nullable.
  *   ws        : workspace of at least sc_workspace_bytes(H, W, C) bytes.
+ * Trailing arguments (both nullable):
+ *   src       : the H x W x C source image (pitch `pitch`), read and written
+ *               to img before carving (src is not modified); NULL carves img
+ *               in place.
+ *   tune      : host pointer to the launch shape; NULL = the built-in choice.
+ * The arguments before `stream` are those of the problem statement in their
+ * order; src and tune are launch plumbing and come last.
  */
-sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
-                   int32_t* seams_out, int64_t* costs_out, const sc_tune* tune, void* ws, size_t ws_bytes,
-                   void* stream);
+sc_status sc_carve(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out, int64_t* costs_out,
+                   void* ws, size_t ws_bytes, void* stream, const uint8_t* src, const sc_tune* tune);
 
 /*
  * Seam insertion (the "Image Enlargement" subsection of the applications
@@ -173,11 +181,11 @@ sc_status sc_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, in
 
 /* One image of a batch (host struct; its pointers are device pointers). */
 typedef struct {
-    const uint8_t* src; /* nullable, as in sc_carve */
     uint8_t* img;
     int H, W, C, pitch, target_w;
-    int32_t* seams_out; /* nullable */
-    int64_t* costs_out; /* nullable */
+    int32_t* seams_out;  /* nullable */
+    int64_t* costs_out;  /* nullable */
+    const uint8_t* src;  /* nullable, as in sc_carve (launch plumbing, last) */
 } sc_job;
 
 /* Workspace bytes for a batch of n jobs (host array). 0 on bad args. */
@@ -189,8 +197,8 @@ typedef struct {
     int nblocks;  /* workgroups of the carve launch */
     int variant;  /* kernel variant */
     int max_rows; /* tallest image */
-    int team;     /* workgroups per image */
-    int pad0;
+    int team;       /* largest team of workgroups for one image */
+    int teams_used; /* images carved by a team of more than one workgroup */
     size_t off_imgs, off_blk, off_teams, off_team_imgs; /* plan arrays inside ws */
 } sc_batch_info;
 
@@ -247,8 +255,8 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
  * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EUNSUPPORTED, SC_EHIP.
  */
 size_t sc_forward_workspace_bytes(int H, int W, int C);
-sc_status sc_carve_forward(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
-                           int32_t* seams_out, int64_t* costs_out, void* ws, size_t ws_bytes, void* stream);
+sc_status sc_carve_forward(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out,
+                           int64_t* costs_out, void* ws, size_t ws_bytes, void* stream, const uint8_t* src);
 size_t sc_forward_batch_workspace_bytes(const sc_job* jobs, int n);
 sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* ws, size_t ws_bytes, sc_batch_info* info);
 sc_status sc_forward_batch_launch(const sc_batch_info* info, void* ws, void* stream);
@@ -261,9 +269,10 @@ sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, voi
  * Step-wise carving for a serving loop (continuous batching).  A slot table (device memory,
  * sc_slot_table_bytes(n) bytes, caller-owned) holds one image per slot; each image keeps its own
  * workspace (sc_workspace_bytes) and stays on the device between steps.
- *   sc_slot_start  validates the job, writes its descriptor into slot `slot` of the table and
+ *   sc_slot_start  validates the job and 0 <= slot < n_slots (the table's size as passed to
+ *                  sc_slot_table_bytes), writes the job's descriptor into slot `slot` and
  *                  enqueues its energy pass (copying job->src into job->img when src is given).
- *   sc_slot_clear  empties slot `slot` (its workspace may then be reused).
+ *   sc_slot_clear  empties slot `slot` (0 <= slot < n_slots; its workspace may then be reused).
  *   sc_slots_step  advances every non-empty slot of the first n by at most max_seams seams in one
  *                  launch (one workgroup per image) and writes progress[i] = seams removed so far
  *                  (device int32; -1 = device error, -2 = empty slot).  A slot is done when
@@ -276,8 +285,9 @@ sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, voi
  *                  instead of waiting for the one with the most work.
  */
 size_t sc_slot_table_bytes(int n_slots);
-sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int slot, void* stream);
-sc_status sc_slot_clear(void* table, int slot, void* stream);
+sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int n_slots, int slot,
+                        void* stream);
+sc_status sc_slot_clear(void* table, int n_slots, int slot, void* stream);
 sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream);
 sc_status sc_slots_step_timed(const void* table, int n_slots, int max_seams, long long budget_us, int32_t* progress,
                               void* stream);

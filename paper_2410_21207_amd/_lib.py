@@ -22,17 +22,16 @@ class sc_tune(ctypes.Structure):
 
 
 SC_TUNE_NO_MINSIDE = 1
-SC_TUNE_NO_PRIO = 2
 SC_TUNE_XCD_SHIFT = 8
 
 
 class sc_job(ctypes.Structure):
-    _fields_ = [("src", P), ("img", P), ("H", I), ("W", I), ("C", I), ("pitch", I), ("target_w", I),
-                ("seams_out", P), ("costs_out", P)]
+    _fields_ = [("img", P), ("H", I), ("W", I), ("C", I), ("pitch", I), ("target_w", I),
+                ("seams_out", P), ("costs_out", P), ("src", P)]
 
 
 class sc_batch_info(ctypes.Structure):
-    _fields_ = [("n", I), ("nblocks", I), ("variant", I), ("max_rows", I), ("team", I), ("pad0", I),
+    _fields_ = [("n", I), ("nblocks", I), ("variant", I), ("max_rows", I), ("team", I), ("teams_used", I),
                 ("off_imgs", Z), ("off_blk", Z), ("off_teams", Z), ("off_team_imgs", Z)]
 
 
@@ -42,12 +41,12 @@ SIGNATURES = {
     "sc_version": (ctypes.c_char_p, []),
     "sc_workspace_bytes": (Z, [I, I, I]),
     "sc_energy": (I, [P, I, I, I, I, P, P]),
-    "sc_dp_seam": (I, [P, I, I, P, P, P, P, Z, P]),
+    "sc_dp_seam": (I, [P, I, I, P, P, P, Z, P, P]),
     "sc_remove_seam": (I, [P, I, I, I, I, P, P]),
     "sc_transpose_u8": (I, [P, I, I, I, I, P, I, P]),
     "sc_variant_count": (I, []),
     "sc_variant_name": (ctypes.c_char_p, [I]),
-    "sc_carve": (I, [P, P, I, I, I, I, I, P, P, ctypes.POINTER(sc_tune), P, Z, P]),
+    "sc_carve": (I, [P, I, I, I, I, I, P, P, P, Z, P, P, ctypes.POINTER(sc_tune)]),
     "sc_insert_workspace_bytes": (Z, [I, I, I, I, I]),
     "sc_insert_seams": (I, [P, I, I, I, I, I, P, I, P, ctypes.POINTER(sc_tune), P, Z, P]),
     "sc_batch_workspace_bytes": (Z, [ctypes.POINTER(sc_job), I]),
@@ -58,7 +57,7 @@ SIGNATURES = {
     "sc_batch_launch_carve": (I, [ctypes.POINTER(sc_batch_info), P, P]),
     "sc_carve_batch": (I, [ctypes.POINTER(sc_job), I, ctypes.POINTER(sc_tune), P, Z, P]),
     "sc_forward_workspace_bytes": (Z, [I, I, I]),
-    "sc_carve_forward": (I, [P, P, I, I, I, I, I, P, P, P, Z, P]),
+    "sc_carve_forward": (I, [P, I, I, I, I, I, P, P, P, Z, P, P]),
     "sc_forward_batch_workspace_bytes": (Z, [ctypes.POINTER(sc_job), I]),
     "sc_forward_batch_prepare": (I, [ctypes.POINTER(sc_job), I, P, Z, ctypes.POINTER(sc_batch_info)]),
     "sc_forward_batch_launch": (I, [ctypes.POINTER(sc_batch_info), P, P]),
@@ -69,8 +68,8 @@ SIGNATURES = {
                           ctypes.POINTER(ctypes.c_double)]),
     "sc_read_stages": (I, [P, ctypes.POINTER(ctypes.c_uint64), I]),
     "sc_slot_table_bytes": (Z, [I]),
-    "sc_slot_start": (I, [ctypes.POINTER(sc_job), P, Z, P, I, P]),
-    "sc_slot_clear": (I, [P, I, P]),
+    "sc_slot_start": (I, [ctypes.POINTER(sc_job), P, Z, P, I, I, P]),
+    "sc_slot_clear": (I, [P, I, I, P]),
     "sc_slots_step": (I, [P, I, I, P, P]),
     "sc_slots_step_timed": (I, [P, I, I, ctypes.c_longlong, P, P]),
 }

@@ -35,6 +35,16 @@ def _image(t: torch.Tensor, name="img"):
     return H, W, C, t.stride(0)
 
 
+def _check_status(ws: torch.Tensor, n: int, what: str):
+    """Raise ScError when any image of the workspace reports a device-side failure (a team barrier
+    that timed out, a team not placed on one XCD): its results are then invalid."""
+    flags = read_status(ws, n)
+    bad = [(i, f) for i, f in enumerate(flags) if f]
+    if bad:
+        raise _lib.ScError(_lib.SC_EHIP, what, f"device status of images {bad[:8]} (1 = team barrier timed out, "
+                                              "2 = team not on one XCD): results invalid")
+
+
 def workspace(nbytes: int, device) -> torch.Tensor:
     """A fresh byte buffer for a workspace (the caching allocator aligns blocks to >= 512 B)."""
     ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -56,8 +66,10 @@ def energy(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> t
     return out
 
 
-def dp_seam(e: torch.Tensor, dirs: bool = False, ws: torch.Tensor | None = None, stream=None):
-    """Minimum vertical seam of an int32 [H, W] energy map -> (seam int32 [H], cost int64 [1][, dirs uint8 [H, W]])."""
+def dp_seam(e: torch.Tensor, dirs: bool = False, ws: torch.Tensor | None = None, stream=None, check: bool = True):
+    """Minimum vertical seam of an int32 [H, W] energy map -> (seam int32 [H], cost int64 [1][, dirs uint8 [H, W]]).
+
+    check: read the device status afterwards (synchronises) and raise ScError on a device failure."""
     if e.dtype != torch.int32 or e.dim() != 2 or not e.is_cuda:
         raise ValueError("energy must be an int32 [H, W] GPU tensor")
     e = e.contiguous()
@@ -69,7 +81,9 @@ def dp_seam(e: torch.Tensor, dirs: bool = False, ws: torch.Tensor | None = None,
     seam = torch.empty(H, dtype=torch.int32, device=e.device)
     cost = torch.empty(1, dtype=torch.int64, device=e.device)
     d = torch.empty((H, W), dtype=torch.uint8, device=e.device) if dirs else None
-    _lib.call("sc_dp_seam", _ptr(e), H, W, _ptr(seam), _ptr(cost), _ptr(d), _ptr(ws), ws.numel(), _stream(stream))
+    _lib.call("sc_dp_seam", _ptr(e), H, W, _ptr(seam), _ptr(cost), _ptr(ws), ws.numel(), _stream(stream), _ptr(d))
+    if check:
+        _check_status(ws, 1, "sc_dp_seam")
     return (seam, cost, d) if dirs else (seam, cost)
 
 
@@ -114,10 +128,12 @@ def _tune(team=None, variant=None, minside=True, xcd=0):
 
 def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, record: bool = True,
           team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None,
-          minside: bool = True):
+          minside: bool = True, check: bool = True):
     """Carve `img` to target_w columns (in place; from `src` when given).
 
     Returns (img[:, :target_w], seams int32 [k, H] or None, costs int64 [k] or None).
+    check: read the device status afterwards (synchronises the device) and raise ScError when the
+    carve failed on the device; with check=False the caller reads it (read_status on `ws`).
     """
     H, W, C, pitch = _image(img)
     if src is not None:
@@ -136,8 +152,10 @@ def carve(img: torch.Tensor, target_w: int, src: torch.Tensor | None = None, rec
     if record and k > 0:
         seams = torch.empty((k, H), dtype=torch.int32, device=img.device)
         costs = torch.empty(k, dtype=torch.int64, device=img.device)
-    _lib.call("sc_carve", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
-              _tune(team, variant, minside), _ptr(ws), ws.numel(), _stream(stream))
+    _lib.call("sc_carve", _ptr(img), H, W, C, int(target_w), pitch, _ptr(seams), _ptr(costs), _ptr(ws), ws.numel(),
+              _stream(stream), _ptr(src), _tune(team, variant, minside))
+    if check:
+        _check_status(ws, 1, "sc_carve")
     return img[:, : int(target_w)], seams, costs
 
 
@@ -158,16 +176,18 @@ def carve_forward(img: torch.Tensor, target_w: int, src: torch.Tensor | None = N
     if record and k > 0:
         seams = torch.empty((k, H), dtype=torch.int32, device=img.device)
         costs = torch.empty(k, dtype=torch.int64, device=img.device)
-    _lib.call("sc_carve_forward", _ptr(src), _ptr(img), H, W, C, pitch, int(target_w), _ptr(seams), _ptr(costs),
-              _ptr(ws), ws.numel(), _stream(stream))
+    _lib.call("sc_carve_forward", _ptr(img), H, W, C, int(target_w), pitch, _ptr(seams), _ptr(costs), _ptr(ws),
+              ws.numel(), _stream(stream), _ptr(src))
     return img[:, : int(target_w)], seams, costs
 
 
 def insert_seams(img: torch.Tensor, k: int, out: torch.Tensor | None = None, record: bool = True,
-                 team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None):
+                 team: int | None = None, variant: int | None = None, ws: torch.Tensor | None = None, stream=None,
+                 check: bool = True):
     """Widen `img` by k seams (img is not modified).
 
     Returns (out [H, W + k, C], original seam columns int32 [k, H] or None).
+    check: as in carve (the seam search is a carve whose workspace starts the insertion workspace).
     """
     H, W, C, pitch = _image(img)
     k = int(k)
@@ -188,6 +208,8 @@ def insert_seams(img: torch.Tensor, k: int, out: torch.Tensor | None = None, rec
     seams = torch.empty((k, H), dtype=torch.int32, device=img.device) if record and k > 0 else None
     _lib.call("sc_insert_seams", _ptr(img), H, W, C, pitch, k, _ptr(out), opitch, _ptr(seams),
               _tune(team, variant), _ptr(ws), ws.numel(), _stream(stream))
+    if check and k > 0:
+        _check_status(ws, 1, "sc_insert_seams")
     return out, seams
 
 
@@ -261,7 +283,7 @@ class BatchCarver:
     """
 
     def __init__(self, imgs, targets, srcs=None, record: bool = True, team: int | None = None,
-                 variant: int | None = None, minside: bool = True, prio: bool = True):
+                 variant: int | None = None, minside: bool = True):
         self.jobs = []
         for i, (img, tw) in enumerate(zip(imgs, targets)):
             H, W, C, pitch = _image(img)
@@ -281,11 +303,12 @@ class BatchCarver:
         self._cjobs = (_lib.sc_job * n)()
         for i, j in enumerate(self.jobs):
             H, W, C, pitch = _image(j.img)
-            self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
-                                         pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
-                                         None if j.costs is None else j.costs.data_ptr())
+            self._cjobs[i] = _lib.sc_job(j.img.data_ptr(), H, W, C, pitch, j.target_w,
+                                         None if j.seams is None else j.seams.data_ptr(),
+                                         None if j.costs is None else j.costs.data_ptr(),
+                                         None if j.src is None else j.src.data_ptr())
         self._tune = _lib.sc_tune(team or 0, -1 if variant is None else variant,
-                                  (0 if minside else _lib.SC_TUNE_NO_MINSIDE) | (0 if prio else _lib.SC_TUNE_NO_PRIO))
+                                  0 if minside else _lib.SC_TUNE_NO_MINSIDE)
         need = _lib.load().sc_batch_workspace_bytes(self._cjobs, n)
         if need == 0:
             raise ValueError("bad batch")
@@ -332,7 +355,11 @@ class BatchCarver:
     def replay(self):
         self.graph.replay()
 
-    def results(self):
+    def results(self, check: bool = True):
+        """[(img[:, :target_w], seams, costs)] per job.  check: read the device status first
+        (synchronises) and raise ScError if any image failed on the device."""
+        if check:
+            _check_status(self.ws, len(self.jobs), "sc_batch_launch")
         return [(j.img[:, : j.target_w], j.seams, j.costs) for j in self.jobs]
 
     def status(self):
@@ -361,9 +388,10 @@ class ForwardBatch:
         self._cjobs = (_lib.sc_job * n)()
         for i, j in enumerate(self.jobs):
             H, W, C, pitch = _image(j.img)
-            self._cjobs[i] = _lib.sc_job(None if j.src is None else j.src.data_ptr(), j.img.data_ptr(), H, W, C,
-                                         pitch, j.target_w, None if j.seams is None else j.seams.data_ptr(),
-                                         None if j.costs is None else j.costs.data_ptr())
+            self._cjobs[i] = _lib.sc_job(j.img.data_ptr(), H, W, C, pitch, j.target_w,
+                                         None if j.seams is None else j.seams.data_ptr(),
+                                         None if j.costs is None else j.costs.data_ptr(),
+                                         None if j.src is None else j.src.data_ptr())
         need = _lib.load().sc_forward_batch_workspace_bytes(self._cjobs, n)
         if need == 0:
             raise ValueError("bad batch")
@@ -392,5 +420,7 @@ class ForwardBatch:
         """Per-image seconds in (DP sweep, argmin + backtrack, removal) of the last carve."""
         return read_stages(self.ws, len(self.jobs))
 
-    def results(self):
+    def results(self, check: bool = True):
+        if check:
+            _check_status(self.ws, len(self.jobs), "sc_forward_batch_launch")
         return [(j.img[:, : j.target_w], j.seams, j.costs) for j in self.jobs]

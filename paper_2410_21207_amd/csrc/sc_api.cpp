@@ -164,8 +164,8 @@ sc_status sc_energy(const uint8_t* img, int H, int W, int C, int pitch, int32_t*
     return ok();
 }
 
-sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, uint8_t* dirs_out, void* ws,
-                     size_t ws_bytes, void* stream) {
+sc_status sc_dp_seam(const int32_t* energy, int H, int W, int32_t* seam, int64_t* cost, void* ws, size_t ws_bytes,
+                     void* stream, uint8_t* dirs_out) {
     sc_status s = check_image(H, W, 1, W);
     if (s != SC_OK) return s;
     if (!energy || !seam || !cost || !ws) return fail(SC_EINVAL, "null pointer");
@@ -208,9 +208,8 @@ sc_status sc_transpose_u8(const uint8_t* src, int H, int W, int C, int src_pitch
     return ok();
 }
 
-sc_status sc_carve(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
-                   int32_t* seams_out, int64_t* costs_out, const sc_tune* tune, void* ws, size_t ws_bytes,
-                   void* stream) {
+sc_status sc_carve(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out, int64_t* costs_out,
+                   void* ws, size_t ws_bytes, void* stream, const uint8_t* src, const sc_tune* tune) {
     sc_status s = check_image(H, W, C, pitch);
     if (s != SC_OK) return s;
     if (!img || !ws) return fail(SC_EINVAL, "null pointer");
@@ -285,9 +284,9 @@ sc_status sc_insert_seams(const uint8_t* img, int H, int W, int C, int pitch, in
     hipStream_t st = (hipStream_t)stream;
     if (k > 0) {
         // the seams: carve a copy (img is the source and stays unmodified), recording each seam
-        s = sc_carve(img, reinterpret_cast<uint8_t*>(base + L.scratch), H, W, C, pitch, W - k,
-                     reinterpret_cast<int32_t*>(base + L.cur), nullptr, tune, base + L.carve,
-                     sc_workspace_bytes(H, W, C), stream);
+        s = sc_carve(reinterpret_cast<uint8_t*>(base + L.scratch), H, W, C, W - k, pitch,
+                     reinterpret_cast<int32_t*>(base + L.cur), nullptr, base + L.carve, sc_workspace_bytes(H, W, C),
+                     stream, img, tune);
         if (s != SC_OK) return s;
         hipError_t e = sc::launch_seam_origins(reinterpret_cast<const int32_t*>(base + L.cur), k, H, W,
                                                reinterpret_cast<int32_t*>(base + L.tree), orig, st);
@@ -369,19 +368,6 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
         }
         gsz[crit] = std::min(std::min(2 * G, 32), per_xcd);
     }
-    // Wave priorities: an image's latency grows with its row chain, seams x rows; images whose
-    // chain is within 2x, 4x, 8x of the longest get priority 3, 2, 1 on their SIMDs.
-    std::vector<int> prio(n, 0);
-    {
-        std::vector<double> chain(n);
-        double cmax = 1;
-        for (int i = 0; i < n; ++i) {
-            chain[i] = (double)(jobs[i].W - jobs[i].target_w) * (jobs[i].H + 64);
-            cmax = std::max(cmax, chain[i]);
-        }
-        for (int i = 0; i < n; ++i)
-            prio[i] = chain[i] * 2 >= cmax ? 3 : chain[i] * 4 >= cmax ? 2 : chain[i] * 8 >= cmax ? 1 : 0;
-    }
     std::vector<int2> blk, teams;
     std::vector<int> team_imgs;
     int slots[8] = {0};
@@ -439,7 +425,6 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
         imgs[i] = make_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
                            base + off_data, ctl, sc::variant(v).kr, gsz[i], 0);
         if (tune && (tune->flags & SC_TUNE_NO_MINSIDE)) imgs[i].minside = 0;
-        if (!(tune && (tune->flags & SC_TUNE_NO_PRIO))) imgs[i].prio = prio[i];
         off_data += sc::layout_for(j.H, j.W, j.C, 32).total;
         max_rows = std::max(max_rows, j.H);
     }
@@ -455,7 +440,7 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     info->variant = v;
     info->max_rows = max_rows;
     info->team = G;
-    info->pad0 = teams_used;  // images carved by a multi-workgroup team
+    info->teams_used = teams_used;
     info->off_imgs = off_imgs;
     info->off_blk = off_blk;
     info->off_teams = off_teams;
@@ -598,9 +583,10 @@ extern "C" size_t sc_slot_table_bytes(int n_slots) {
     return sc::align_up((size_t)n_slots * kSlotBytes, sc::kAlign);
 }
 
-extern "C" sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int slot,
+extern "C" sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int n_slots, int slot,
                                    void* stream) {
-    if (!job || !ws || !table || slot < 0) return fail(SC_EINVAL, "null pointer or negative slot");
+    if (!job || !ws || !table) return fail(SC_EINVAL, "null pointer");
+    if (n_slots < 1 || slot < 0 || slot >= n_slots) return fail(SC_EINVAL, "slot %d not in [0, %d)", slot, n_slots);
     sc_status s = check_image(job->H, job->W, job->C, job->pitch);
     if (s != SC_OK) return s;
     if (!job->img) return fail(SC_EINVAL, "null image");
@@ -621,8 +607,9 @@ extern "C" sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes,
     return ok();
 }
 
-extern "C" sc_status sc_slot_clear(void* table, int slot, void* stream) {
-    if (!table || slot < 0) return fail(SC_EINVAL, "null table or negative slot");
+extern "C" sc_status sc_slot_clear(void* table, int n_slots, int slot, void* stream) {
+    if (!table) return fail(SC_EINVAL, "null table");
+    if (n_slots < 1 || slot < 0 || slot >= n_slots) return fail(SC_EINVAL, "slot %d not in [0, %d)", slot, n_slots);
     sc::Img d;
     memset(&d, 0, sizeof(d));
     hipError_t e = sc::launch_slot_write(static_cast<sc::Img*>(table), slot, d, (hipStream_t)stream);
@@ -724,9 +711,8 @@ extern "C" size_t sc_forward_workspace_bytes(int H, int W, int C) {
     return ctl_region(1) + fwd_layout(H, W, C).total;
 }
 
-extern "C" sc_status sc_carve_forward(const uint8_t* src, uint8_t* img, int H, int W, int C, int pitch, int target_w,
-                                      int32_t* seams_out, int64_t* costs_out, void* ws, size_t ws_bytes,
-                                      void* stream) {
+extern "C" sc_status sc_carve_forward(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out,
+                                      int64_t* costs_out, void* ws, size_t ws_bytes, void* stream, const uint8_t* src) {
     sc_status s = check_fwd_image(H, W, C, pitch);
     if (s != SC_OK) return s;
     if (!img || !ws) return fail(SC_EINVAL, "null pointer");

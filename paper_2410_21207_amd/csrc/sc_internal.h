@@ -31,7 +31,6 @@ struct Img {
     int G;                     // team size (workgroups) carving this image
     int mode;                  // 0 = carve, 1 = one seam only, no removal (sc_dp_seam)
     int minside;               // 1 = remove a seam pixel by moving the shorter side of its row
-    int prio;                  // wave priority (0..3) of the workgroups carving this image
 };
 
 // Control words of one image (zeroed by the energy pass of every launch).

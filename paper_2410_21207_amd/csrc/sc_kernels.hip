@@ -455,18 +455,6 @@ __device__ __forceinline__ void copy_bytes_wave(uint8_t* dst, const uint8_t* src
     }
 }
 
-// Issue priority of the calling wave against the other waves on its SIMD (0 lowest .. 3).  The
-// batch planner raises it for the images on the batch's critical path, so their row chains are
-// not slowed by the short images sharing their compute units.
-__device__ __forceinline__ void set_prio(int p) {
-    switch (p) {
-        case 3: __builtin_amdgcn_s_setprio(3); break;
-        case 2: __builtin_amdgcn_s_setprio(2); break;
-        case 1: __builtin_amdgcn_s_setprio(1); break;
-        default: __builtin_amdgcn_s_setprio(0); break;
-    }
-}
-
 // Standalone seam removal: one wave per row.
 __global__ void remove_seam_kernel(uint8_t* __restrict__ img, int H, int W, int C, long long pitch,
                                    const int32_t* __restrict__ seam) {
@@ -1050,7 +1038,6 @@ struct Carver {
     static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams,
                                                        unsigned long long deadline = 0) {
         Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
-        set_prio(d.prio);
         const int nseams = d.mode ? 1 : d.W - d.target_w;
         const int k0 = max_seams > 0 ? (int)ctl->done : 0;
         const int k1 = max_seams > 0 ? min(nseams, k0 + max_seams) : nseams;

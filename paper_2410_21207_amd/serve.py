@@ -209,42 +209,24 @@ class Server:
 class GPUExecutor:
     """Device side of the server: one slot table, per-request device image + workspace.
 
-    A request of at least `big_work` pixel-seams that arrives while one of the `big_streams` side
-    streams is idle is not stepped in the slot table: a team of workgroups (sc_carve, launch
-    shape from the autotuner, at most 16 workgroups) carves it whole on that stream, stream i
-    placing its team on XCD i, concurrently with the step kernel; an event tells when it is done.
-    Otherwise it is stepped like any other request, so admission never waits for a side stream.
-    Off by default (big_work None): on the Poisson serving mix it measured no gain, the server
-    being bound by its step throughput rather than by its largest requests.
+    Every admitted request is stepped in the slot table (one workgroup per image in each step
+    launch); a device failure of a slot comes back as a negative progress value, which the server
+    turns into an error for that request alone.
     """
 
-    def __init__(self, max_slots: int, device="cuda", big_work: float | None = None, big_streams: int = 2):
+    def __init__(self, max_slots: int, device="cuda"):
         import torch
 
-        from . import _lib, api, tune
-        self.torch, self._lib, self.lib, self.api, self.tune = torch, _lib, _lib.load(), api, tune
+        from . import _lib, api
+        self.torch, self._lib, self.lib, self.api = torch, _lib, _lib.load(), api
         self.device = torch.device(device)
         self.max_slots = max_slots
         self.table = torch.zeros(self.lib.sc_slot_table_bytes(max_slots), dtype=torch.uint8, device=self.device)
         self.progress = torch.zeros(max_slots, dtype=torch.int32, device=self.device)
         self.progress_host = torch.zeros(max_slots, dtype=torch.int32).pin_memory()
         self.state = [None] * max_slots
-        # a stream of its own for the steps; with the side streams this stays within the hardware
-        # queues a process gets, so a step never queues behind a long side carve
+        # a stream of its own for the steps (default priority)
         self.stream = torch.cuda.Stream(self.device)
-        self.big_work = big_work
-        self.big_streams = [torch.cuda.Stream(self.device) for _ in range(max(0, big_streams))]
-        self.big_busy = [None] * len(self.big_streams)  # slot carving on each side stream
-        self.big = {}                                     # slot -> (done event, seams, stream index)
-
-    def _big_stream(self):
-        for i, b in enumerate(self.big_busy):
-            if b is None:
-                return i
-        return None
-
-    def _is_big(self, t: "Ticket") -> bool:
-        return self.big_work is not None and len(self.big_streams) > 0 and t.pixel_seams >= self.big_work
 
     def state_bytes(self, h, w, c, target_w):
         """HBM a request holds while admitted: source and image, workspace, seam log and costs."""
@@ -265,25 +247,13 @@ class GPUExecutor:
         seams = torch.empty((max(k, 1), t.h), dtype=torch.int32, device=self.device)
         costs = torch.empty(max(k, 1), dtype=torch.int64, device=self.device)
         self.state[slot] = (src, img, ws, seams, costs, t.target_w, k)
-        i = self._big_stream() if self._is_big(t) else None
-        if i is not None:  # a big request and a free side stream: a team carves it whole
-            s = self.big_streams[i]
-            s.wait_stream(caller)
-            variant, team = api._tuned(self.device, lambda a: self.tune.key_single(a, t.h, t.w))
-            _lib.call("sc_carve", ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(img.data_ptr()), t.h, t.w, t.c,
-                      src.stride(0), t.target_w, ctypes.c_void_p(seams.data_ptr()), ctypes.c_void_p(costs.data_ptr()),
-                      api._tune(min(team or 16, 16), variant, True, xcd=i), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                      ctypes.c_void_p(s.cuda_stream))
-            ev = torch.cuda.Event()
-            ev.record(s)
-            self.big[slot] = (ev, k, i)
-            self.big_busy[i] = slot
-            return
-        job = _lib.sc_job(src.data_ptr(), img.data_ptr(), t.h, t.w, t.c, src.stride(0), t.target_w,
-                          seams.data_ptr(), costs.data_ptr())
+        job = _lib.sc_job(img.data_ptr(), t.h, t.w, t.c, src.stride(0), t.target_w, seams.data_ptr(),
+                          costs.data_ptr(), src.data_ptr())
+        # every payload written on the caller's stream is awaited by the step stream
         self.stream.wait_stream(caller)
         _lib.call("sc_slot_start", ctypes.byref(job), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                  ctypes.c_void_p(self.table.data_ptr()), slot, ctypes.c_void_p(self.stream.cuda_stream))
+                  ctypes.c_void_p(self.table.data_ptr()), self.max_slots, slot,
+                  ctypes.c_void_p(self.stream.cuda_stream))
 
     def advance(self, n, max_seams, budget_us: int = 0):
         self._lib.call("sc_slots_step_timed", ctypes.c_void_p(self.table.data_ptr()), n, max_seams, int(budget_us),
@@ -291,24 +261,15 @@ class GPUExecutor:
         with self.torch.cuda.stream(self.stream):  # ordered after the step on the same stream
             self.progress_host[:n].copy_(self.progress[:n], non_blocking=True)
         self.stream.synchronize()
-        prog = self.progress_host.tolist()
-        for slot, (ev, k, _) in self.big.items():  # side-stream carves: all seams or none yet
-            if slot < n:
-                prog[slot] = k if ev.query() else 0
-        return prog
+        return self.progress_host.tolist()
 
     def result(self, slot):
         src, img, ws, seams, costs, tw, k = self.state[slot]
         return img[:, :tw], (seams if k > 0 else None), (costs if k > 0 else None)
 
     def release(self, slot):
-        if slot in self.big:
-            ev, _, i = self.big.pop(slot)
-            ev.synchronize()
-            self.big_busy[i] = None
-        else:
-            self._lib.call("sc_slot_clear", ctypes.c_void_p(self.table.data_ptr()), slot,
-                           ctypes.c_void_p(self.stream.cuda_stream))
+        self._lib.call("sc_slot_clear", ctypes.c_void_p(self.table.data_ptr()), self.max_slots, slot,
+                       ctypes.c_void_p(self.stream.cuda_stream))
         self.state[slot] = None
 
 
@@ -322,9 +283,6 @@ def main():
     ap.add_argument("--step-us", type=int, default=20000,
                     help="time budget of a step in microseconds (0: every slot removes seams-per-step seams)")
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--big-work", type=float, default=0,
-                    help="requests of at least this many pixel-seams are carved whole by a team on a side stream "
-                         "(0: step every request in the slot table)")
     args = ap.parse_args()
 
     import torch
@@ -338,7 +296,7 @@ def main():
     def payload(r):  # a request's pixels: a crop of a device-resident canvas (no PCIe in the loop)
         return canvases[r.canvas][r.y0:r.y0 + r.h, r.x0:r.x0 + r.w].contiguous()
 
-    srv = Server(GPUExecutor(args.slots, dev, big_work=args.big_work or None), budget_bytes=int(args.budget_gb * 1e9),
+    srv = Server(GPUExecutor(args.slots, dev), budget_bytes=int(args.budget_gb * 1e9),
                  max_slots=args.slots,
                  seams_per_step=args.seams_per_step, step_budget_us=args.step_us)
     st = srv.run(reqs, payload, progress=lambda m: print(m, file=sys.stderr, flush=True))
@@ -347,7 +305,7 @@ def main():
     st.update({"workload": f"Poisson {args.rate}/s for {args.duration}s, sides log-uniform [128,4096], "
                            "target 50-90% of width, 64 GB budget",
                "offered_pixel_seams_per_s": round(offered, 1), "seams_per_step": args.seams_per_step,
-               "big_work": args.big_work, "step_us": args.step_us,
+               "step_us": args.step_us,
                "slots": args.slots})
     print(json.dumps(st), flush=True)
 
