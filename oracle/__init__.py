@@ -77,11 +77,16 @@ class Oracle:
             "sco_brute_seam": [P, I, I, P, P],
             "sco_forward_dp": [P, I, I, I, I, P, P, P, P],
             "sco_carve_forward": [P, I, I, I, I, I, P, P],
+            "sco_object_direction": [P, I, I, I],
+            "sco_masked_seam": [P, P, I, I, I, I, I, ctypes.c_int32, P, P],
+            "sco_remove_object": [P, P, I, I, I, I, I, I, I, P, I, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
             f.argtypes = args
             f.restype = ctypes.c_int
+        lib.sco_mask_bias.argtypes = [I, I]
+        lib.sco_mask_bias.restype = ctypes.c_int32
         self.lib = lib
 
     def energy(self, img) -> np.ndarray:
@@ -194,6 +199,52 @@ class Oracle:
         _check(self.lib.sco_carve_forward(_p(img), H, W, C, W * C, target_w, _p(seams), _p(costs)), "carve_forward")
         return np.ascontiguousarray(img[:, :target_w]), seams, costs
 
+    def mask_bias(self, h: int, C: int) -> int:
+        """The bias B subtracted under the mask for an h-row image of C channels (R20)."""
+        return int(self.lib.sco_mask_bias(h, C))
+
+    def object_direction(self, mask) -> int:
+        """0 (vertical seams) or 1 (horizontal seams) for a uint8 [H, W] mask (R21)."""
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        H, W = mask.shape
+        d = self.lib.sco_object_direction(_p(mask), H, W, W)
+        _check(0 if d >= 0 else d, "object_direction")
+        return int(d)
+
+    def masked_seam(self, img, mask, B: int):
+        """Minimum vertical seam of img with B subtracted from the e1 energy under the mask (R20)
+        -> (seam int32 [H], cost int)."""
+        img = _img(img)
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        H, W, C = img.shape
+        assert mask.shape == (H, W)
+        seam = np.empty(H, np.int32)
+        cost = np.zeros(1, np.int64)
+        _check(self.lib.sco_masked_seam(_p(img), _p(mask), H, W, C, W * C, W, int(B), _p(seam), _p(cost)),
+               "masked_seam")
+        return seam, int(cost[0])
+
+    def remove_object(self, img, mask, direction: int = -1, restore: bool = False):
+        """Remove the object under `mask` (R20-R24).
+
+        Returns (out uint8 [oh, ow, C], info dict, seams int32 [k, h], costs int64 [k]); seams are
+        in the carved frame (h = H for vertical seams, W for horizontal ones)."""
+        img = _img(img)
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        H, W, C = img.shape
+        assert mask.shape == (H, W)
+        out = np.zeros((H, W, C), np.uint8)
+        info = np.zeros(5, np.int32)
+        seams = np.zeros(H * W, np.int32)
+        costs = np.zeros(max(H, W), np.int64)
+        _check(self.lib.sco_remove_object(_p(img), _p(mask), H, W, C, W * C, W, int(direction), int(bool(restore)),
+                                          _p(out), W * C, _p(info), _p(seams), _p(costs)), "remove_object")
+        d, k, oh, ow, left = (int(v) for v in info)
+        h = H if d == 0 else W
+        res = np.ascontiguousarray(out.reshape(-1)[: oh * W * C].reshape(oh, W, C)[:, :ow])
+        return res, {"direction": d, "k": k, "rows": oh, "cols": ow, "left": left}, \
+            seams[: k * h].reshape(k, h), costs[:k]
+
     def greedy_seam(self, e):
         """Alg. 2 greedy seam of an int32 [H, W] energy map -> (seam, cost)."""
         e = np.ascontiguousarray(np.asarray(e, dtype=np.int32))
@@ -254,6 +305,22 @@ def insert_seams(img, k: int):
 
 def greedy_seam(e):
     return default().greedy_seam(e)
+
+
+def mask_bias(h: int, C: int):
+    return default().mask_bias(h, C)
+
+
+def object_direction(mask):
+    return default().object_direction(mask)
+
+
+def masked_seam(img, mask, B: int):
+    return default().masked_seam(img, mask, B)
+
+
+def remove_object(img, mask, direction: int = -1, restore: bool = False):
+    return default().remove_object(img, mask, direction, restore)
 
 
 def brute_seam(e):

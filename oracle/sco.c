@@ -470,3 +470,187 @@ int sco_brute_seam(const int32_t* e, int H, int W, int32_t* seam, int64_t* cost)
     *cost = c.best_cost;
     return SCO_OK;
 }
+
+/*
+ * ---------------------------------------------------------------------------
+ * Object removal with a binary mask (sec. "Object Removal" among the
+ * applications), readings R20-R24 (each listed in the design doc):
+ *   R20 the "very high negative value" under the mask: B = h*510*C + 1 is
+ *       subtracted from the e1 energy of every masked pixel, h being the rows
+ *       of the image being carved.  B exceeds the e1 energy of any seam
+ *       (510*C per pixel at most), so one more masked pixel on a seam always
+ *       outweighs all the energy elsewhere on it: the minimum seam is the one
+ *       with the most masked pixels, then the least energy, then R5/R6 ties.
+ *       Any larger B selects the same seams.
+ *   R21 the direction, chosen from the mask's extent: its bounding box is h_m
+ *       rows by w_m columns; a vertical seam deletes one pixel per row, so
+ *       about w_m of them remove the object, and a horizontal one about h_m.
+ *       Vertical seams when w_m <= h_m (or the mask is empty), horizontal
+ *       seams (R10: carve the transpose) otherwise.
+ *   R22 the loop: while a masked pixel remains and the image has more than
+ *       one column, remove the minimum seam of the current image from the
+ *       image and from the mask alike (the mask is shifted as the pixels are).
+ *   R23 restoring the size: the k removed columns come back by seam insertion
+ *       on the reduced image (R15, R16); when k is not below the reduced
+ *       width w, in rounds of at most (current width - 1) seams, since one
+ *       round records its seams by carving the current image.  A reduced
+ *       width of 1 cannot be enlarged this way (error).
+ *   R24 the mask is one byte per pixel; any nonzero byte marks the pixel.
+ * ---------------------------------------------------------------------------
+ */
+#define SCO_OBJ_AUTO (-1)
+#define SCO_OBJ_VERTICAL 0
+#define SCO_OBJ_HORIZONTAL 1
+
+/* The mask bias of R20 for an h-row image of C channels. */
+int32_t sco_mask_bias(int h, int C) { return (int32_t)h * 510 * C + 1; }
+
+/* R21: SCO_OBJ_VERTICAL or SCO_OBJ_HORIZONTAL for an H x W mask (mpitch bytes per row). */
+int sco_object_direction(const uint8_t* mask, int H, int W, int mpitch) {
+    if (!mask || H < 1 || W < 1 || mpitch < W) return SCO_EINVAL;
+    int r0 = H, r1 = -1, c0 = W, c1 = -1;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            if (mask[(size_t)y * mpitch + x]) {
+                if (y < r0) r0 = y;
+                if (y > r1) r1 = y;
+                if (x < c0) c0 = x;
+                if (x > c1) c1 = x;
+            }
+    if (r1 < 0) return SCO_OBJ_VERTICAL;
+    return (c1 - c0 + 1) <= (r1 - r0 + 1) ? SCO_OBJ_VERTICAL : SCO_OBJ_HORIZONTAL;
+}
+
+/*
+ * One masked seam (R20): the e1 energy of the current image (sco_energy),
+ * minus B at every masked pixel, then the minimum seam of sco_dp (the DP
+ * recurrence of Alg. 3 with R3-R7).  B is an argument so that the tests can
+ * show that every B above the bound gives the same seam; the removal loop
+ * passes sco_mask_bias(H, C).  cost = sum over the seam of e - B*[masked].
+ */
+int sco_masked_seam(const uint8_t* img, const uint8_t* mask, int H, int W, int C, int pitch, int mpitch, int32_t B,
+                    int32_t* seam, int64_t* cost) {
+    if (!img || !mask || !seam || !cost || H < 1 || W < 1 || C < 1 || pitch < W * C || mpitch < W || B < 0)
+        return SCO_EINVAL;
+    int32_t* e = (int32_t*)malloc(sizeof(int32_t) * (size_t)H * W);
+    if (!e) return SCO_ENOMEM;
+    int rc = sco_energy(img, H, W, C, pitch, e);
+    if (rc == SCO_OK) {
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x)
+                if (mask[(size_t)y * mpitch + x]) e[(size_t)y * W + x] -= B;
+        rc = sco_dp(e, H, W, NULL, NULL, seam, cost);
+    }
+    free(e);
+    return rc;
+}
+
+static long long count_mask(const uint8_t* mask, int H, int W, int mpitch) {
+    long long n = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) n += mask[(size_t)y * mpitch + x] != 0;
+    return n;
+}
+
+/*
+ * Remove the object under `mask` (H x W, mpitch bytes per row) from img
+ * (H x W x C, pitch bytes per row), readings R20-R24, in the order the
+ * section describes: choose the direction, carve masked seams until the mask
+ * is gone, then (restore != 0) insert as many seams to get the size back.
+ *   direction : SCO_OBJ_AUTO (R21), SCO_OBJ_VERTICAL or SCO_OBJ_HORIZONTAL.
+ *   out       : the result, out_pitch bytes per row: H x W x C when restoring;
+ *               else H x (W-k) x C (vertical) or (H-k) x W x C (horizontal).
+ *   info      : 5 int32: direction used, k (seams removed), rows and columns
+ *               of out, masked pixels left (0 unless the carve reached one
+ *               column first).
+ *   seams_out : nullable, H*W int32: seam j at seams_out[j*h + i], i < h, in
+ *               the frame that was carved (h = H vertical, W horizontal) and
+ *               the column coordinates of the image it was removed from.
+ *   costs_out : nullable, max(H, W) int64, the cost of every seam (R20).
+ */
+int sco_remove_object(const uint8_t* img, const uint8_t* mask, int H, int W, int C, int pitch, int mpitch,
+                      int direction, int restore, uint8_t* out, int out_pitch, int32_t* info, int32_t* seams_out,
+                      int64_t* costs_out) {
+    if (!img || !mask || !out || !info || H < 1 || W < 1 || C < 1 || pitch < W * C || mpitch < W ||
+        direction < SCO_OBJ_AUTO || direction > SCO_OBJ_HORIZONTAL)
+        return SCO_EINVAL;
+    const int dir = direction == SCO_OBJ_AUTO ? sco_object_direction(mask, H, W, mpitch) : direction;
+    if (dir < 0) return dir;
+    /* the frame that is carved: h rows of w0 pixels */
+    const int h = dir == SCO_OBJ_VERTICAL ? H : W, w0 = dir == SCO_OBJ_VERTICAL ? W : H;
+    const int ip = w0 * C, mp = w0;
+    uint8_t* I = (uint8_t*)malloc((size_t)h * ip);
+    uint8_t* M = (uint8_t*)malloc((size_t)h * mp);
+    int32_t* s = (int32_t*)malloc(sizeof(int32_t) * (size_t)h);
+    uint8_t* R = NULL;
+    int rc = (I && M && s) ? SCO_OK : SCO_ENOMEM;
+    if (rc == SCO_OK) {
+        if (dir == SCO_OBJ_VERTICAL) {
+            for (int y = 0; y < H; ++y) {
+                memcpy(I + (size_t)y * ip, img + (size_t)y * pitch, (size_t)W * C);
+                memcpy(M + (size_t)y * mp, mask + (size_t)y * mpitch, (size_t)W);
+            }
+        } else {
+            rc = sco_transpose(img, H, W, C, pitch, I, ip);
+            if (rc == SCO_OK) rc = sco_transpose(mask, H, W, 1, mpitch, M, mp);
+        }
+    }
+    const int32_t B = sco_mask_bias(h, C);
+    int w = w0, k = 0;
+    while (rc == SCO_OK && w > 1 && count_mask(M, h, w, mp) > 0) {          /* R22 */
+        int64_t cost = 0;
+        if ((rc = sco_masked_seam(I, M, h, w, C, ip, mp, B, s, &cost)) != SCO_OK) break;
+        if ((rc = sco_remove_seam(I, h, w, C, ip, s)) != SCO_OK) break;
+        if ((rc = sco_remove_seam(M, h, w, 1, mp, s)) != SCO_OK) break;
+        if (seams_out) memcpy(seams_out + (size_t)k * h, s, sizeof(int32_t) * (size_t)h);
+        if (costs_out) costs_out[k] = cost;
+        ++k;
+        --w;
+    }
+    const long long left = rc == SCO_OK ? count_mask(M, h, w, mp) : 0;
+    /* R23: the reduced image (h x w) grows back to h x w0 */
+    int rw = w;
+    const uint8_t* res = I;
+    int res_pitch = ip;
+    if (rc == SCO_OK && restore && k > 0) {
+        if (w < 2) rc = SCO_EINVAL;
+        uint8_t* cur = I;
+        int cur_pitch = ip;
+        while (rc == SCO_OK && rw < w0) {
+            const int n = (w0 - rw) < (rw - 1) ? (w0 - rw) : (rw - 1);
+            uint8_t* nxt = (uint8_t*)malloc((size_t)h * (rw + n) * C);
+            if (!nxt) {
+                rc = SCO_ENOMEM;
+                break;
+            }
+            rc = sco_insert_seams(cur, h, rw, C, cur_pitch, n, nxt, (rw + n) * C, NULL);
+            if (cur != I) free(cur);
+            cur = nxt;
+            cur_pitch = (rw + n) * C;
+            rw += n;
+        }
+        R = cur != I ? cur : NULL;
+        res = cur;
+        res_pitch = cur_pitch;
+    }
+    if (rc == SCO_OK) {
+        const int oh = dir == SCO_OBJ_VERTICAL ? h : rw, ow = dir == SCO_OBJ_VERTICAL ? rw : h;
+        if (out_pitch < ow * C) {
+            rc = SCO_EINVAL;
+        } else if (dir == SCO_OBJ_VERTICAL) {
+            for (int y = 0; y < h; ++y) memcpy(out + (size_t)y * out_pitch, res + (size_t)y * res_pitch, (size_t)rw * C);
+        } else {
+            rc = sco_transpose(res, h, rw, C, res_pitch, out, out_pitch);
+        }
+        info[0] = dir;
+        info[1] = k;
+        info[2] = oh;
+        info[3] = ow;
+        info[4] = (int32_t)left;
+    }
+    free(R);
+    free(I);
+    free(M);
+    free(s);
+    return rc;
+}

@@ -492,3 +492,195 @@ def pin_forward_carve_invariants(o):
 
 
 ALL_PINS += [pin_forward_hand_grids, pin_forward_bruteforce, pin_forward_closed_forms, pin_forward_carve_invariants]
+
+
+# --------------------------------------------------------------------------------------------
+# Object removal with a mask (sec. "Object Removal" among the applications; readings R20-R24)
+
+
+def py_brute_masked(e, mask):
+    """Every connected seam of the energy map e (int [H, W]) under the key
+    (-masked pixels on the seam, energy of the seam, s[H-1], ..., s[0]): the seam through the most
+    masked pixels, then the cheapest, then R5/R6 ties.  This is what any mask bias above the bound
+    of R20 selects, written without a bias at all.  Tiny maps only."""
+    e = np.asarray(e)
+    H, W = e.shape
+    best = None
+    for start in range(W):
+        for moves in itertools.product((-1, 0, 1), repeat=H - 1):
+            path = [start]
+            for mv in moves:
+                path.append(path[-1] + mv)
+            if min(path) < 0 or max(path) >= W:
+                continue
+            rows = [(H - 1 - t, path[t]) for t in range(H)]
+            cnt = sum(1 for (r, c) in rows if mask[r, c])
+            en = sum(int(e[r, c]) for (r, c) in rows)
+            key = (-cnt, en, tuple(path))
+            if best is None or key < best:
+                best = key
+    ncnt, en, path = best
+    return np.array(path[::-1], np.int32), -ncnt, en
+
+
+def _bbox_direction(mask):
+    """R21 from the definition: vertical (0) unless the mask's box is wider than tall."""
+    ys, xs = np.nonzero(mask)
+    if len(ys) == 0:
+        return 0
+    return 0 if (xs.max() - xs.min() + 1) <= (ys.max() - ys.min() + 1) else 1
+
+
+def object_invariants(o, img, mask, direction=-1, restore=False, check_brute=False):
+    """Replay the recorded seams on numpy copies of the image and the mask: every seam is valid,
+    crosses at least one masked pixel while one is left, costs its energy minus B per masked pixel
+    on the current image, and (small cases) is the brute-force masked seam; the loop stops exactly
+    when the mask is gone (or one column is left); the output is the replayed image, in the
+    original orientation; a restored output has the original size and holds the reduced image
+    once its inserted pixels are deleted."""
+    H, W, C = img.shape
+    out, info, seams, costs = o.remove_object(img, mask, direction, restore)
+    d = info["direction"]
+    assert d == (direction if direction >= 0 else _bbox_direction(mask))
+    cur = img.copy() if d == 0 else np.ascontiguousarray(img.transpose(1, 0, 2))
+    m = (mask != 0) if d == 0 else np.ascontiguousarray((mask != 0).T)
+    h = cur.shape[0]
+    B = o.mask_bias(h, C)
+    assert B > h * 510 * C, "the bias must exceed the energy of any seam"
+    k = info["k"]
+    assert seams.shape == (k, h) and costs.shape == (k,)
+    for j in range(k):
+        assert m.any() and cur.shape[1] > 1, "a seam was removed after the mask was gone"
+        s = seams[j]
+        check_seam_valid(s, h, cur.shape[1])
+        on = m[np.arange(h), s]
+        assert on.any(), "a masked seam missed the mask"
+        e = o.energy(cur)
+        assert costs[j] == int(e[np.arange(h), s].sum()) - B * int(on.sum()), ("cost", j)
+        if check_brute:
+            bs, bcnt, ben = py_brute_masked(e, m)
+            assert s.tolist() == bs.tolist() and int(on.sum()) == bcnt, ("brute", j)
+        cur = np.stack([np.delete(cur[i], s[i], axis=0) for i in range(h)])
+        m = np.stack([np.delete(m[i], s[i], axis=0) for i in range(h)])
+    assert info["left"] == int(m.sum())
+    assert not m.any() or cur.shape[1] == 1, "the loop stopped with masked pixels left"
+    if not restore or k == 0:
+        want = cur if d == 0 else np.ascontiguousarray(cur.transpose(1, 0, 2))
+        assert np.array_equal(out, want), "output != input with the seams deleted"
+    else:
+        assert out.shape == (H, W, C)
+        o_frame = out if d == 0 else np.ascontiguousarray(out.transpose(1, 0, 2))
+        # the rounds of R23 on the reduced image, each one the insertion of the image enlargement
+        res, rw = cur, cur.shape[1]
+        while rw < cur.shape[1] + k:
+            n = min(cur.shape[1] + k - rw, rw - 1)
+            res, orig = o.insert_seams(res, n)
+            rw += n
+        assert np.array_equal(o_frame, res), "restored output != insertion rounds on the reduced image"
+    return out, info, seams, costs
+
+
+def pin_object_hand_grid(o):
+    for c in load_golden("object_grids.json")["cases"]:
+        img = np.array(c["img"], np.uint8)
+        mask = np.array(c["mask"], np.uint8)
+        assert o.mask_bias(img.shape[0], img.shape[2]) == c["bias"]
+        out, info, seams, costs = o.remove_object(img, mask)
+        assert info["direction"] == c["direction"] and seams.tolist() == c["seams"], c["name"]
+        assert costs.tolist() == c["costs"], c["name"]
+        assert np.array_equal(out, np.array(c["reduced"], np.uint8)), c["name"]
+        out, info, _, _ = o.remove_object(img, mask, restore=True)
+        assert np.array_equal(out, np.array(c["restored"], np.uint8)), c["name"]
+        # the same object turned 90 degrees: horizontal seams, the transposed results
+        t_img = np.ascontiguousarray(img.transpose(1, 0, 2))
+        out, info, seams, costs = o.remove_object(t_img, np.ascontiguousarray(mask.T), restore=True)
+        assert info["direction"] == 1 - c["direction"] and seams.tolist() == c["seams"], c["name"]
+        assert np.array_equal(out, np.array(c["restored"], np.uint8).transpose(1, 0, 2)), c["name"]
+
+
+def pin_masked_seam_bruteforce(o, n=150, seed=31):
+    """The masked seam equals the lexicographic brute force for the bias of R20 and for any larger
+    one; with no bias it is the e1 seam of the DP section."""
+    rng = np.random.default_rng(seed)
+    for t in range(n):
+        H, W = int(rng.integers(1, 6)), int(rng.integers(1, 6))
+        C = int(rng.integers(1, 4))
+        alpha = [2, 3, 256][t % 3]
+        img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+        mask = (rng.random((H, W)) < [0.1, 0.3, 0.6][t % 3]).astype(np.uint8)
+        e = o.energy(img)
+        bs, bcnt, ben = py_brute_masked(e, mask)
+        B = o.mask_bias(H, C)
+        for b in (B, 3 * B + 7):
+            s, cost = o.masked_seam(img, mask, b)
+            assert s.tolist() == bs.tolist() and cost == ben - b * bcnt, (t, b, img.tolist(), mask.tolist())
+        s0, c0 = o.masked_seam(img, mask, 0)
+        ps, pc = py_brute_seam(e)
+        assert s0.tolist() == ps.tolist() and c0 == pc
+
+
+def pin_object_direction(o):
+    def box(H, W, y0, y1, x0, x1):
+        m = np.zeros((H, W), np.uint8)
+        m[y0:y1, x0:x1] = 1
+        return m
+    assert o.object_direction(np.zeros((5, 7), np.uint8)) == 0            # empty: nothing to choose
+    assert o.object_direction(box(9, 9, 1, 8, 3, 5)) == 0                  # 7 tall, 2 wide
+    assert o.object_direction(box(9, 9, 3, 5, 1, 8)) == 1                  # 2 tall, 7 wide
+    assert o.object_direction(box(9, 9, 2, 6, 2, 6)) == 0                  # square: vertical
+    m = np.zeros((8, 8), np.uint8)
+    m[1, 1] = m[2, 6] = 1                                                  # box 2 tall, 6 wide
+    assert o.object_direction(m) == 1
+    m[7, 3] = 1                                                            # box 7 tall, 6 wide
+    assert o.object_direction(m) == 0
+
+
+def pin_object_invariants(o):
+    rng = np.random.default_rng(33)
+    for (H, W, C) in [(4, 6, 3), (5, 4, 1), (3, 7, 2), (6, 5, 3)]:
+        for alpha in (3, 256):
+            img = rng.integers(0, alpha, size=(H, W, C), dtype=np.uint8)
+            mask = np.zeros((H, W), np.uint8)
+            y0, x0 = int(rng.integers(0, H - 1)), int(rng.integers(0, W - 1))
+            mask[y0:y0 + int(rng.integers(1, H - y0 + 1)), x0:x0 + int(rng.integers(1, 3))] = 1
+            object_invariants(o, img, mask, check_brute=True)
+            object_invariants(o, img, mask, restore=True)
+            object_invariants(o, img, mask, direction=1 - _bbox_direction(mask), check_brute=True)
+    img = rng.integers(0, 256, size=(14, 18, 3), dtype=np.uint8)
+    mask = np.zeros((14, 18), np.uint8)
+    mask[3:11, 7:10] = 1
+    mask[5, 12] = 1
+    object_invariants(o, img, mask, restore=True)
+
+
+def pin_object_edges(o):
+    rng = np.random.default_rng(34)
+    img = rng.integers(0, 256, size=(5, 6, 3), dtype=np.uint8)
+    # no mask: nothing removed, the image back unchanged
+    for restore in (False, True):
+        out, info, seams, costs = o.remove_object(img, np.zeros((5, 6), np.uint8), restore=restore)
+        assert info["k"] == 0 and info["left"] == 0 and np.array_equal(out, img) and seams.shape == (0, 5)
+    # a mask of two whole columns: two seams, each one of those columns, straight down
+    mask = np.zeros((5, 6), np.uint8)
+    mask[:, 1] = mask[:, 4] = 1
+    out, info, seams, costs = object_invariants(o, img, mask, check_brute=True)
+    assert info["k"] == 2 and all(len(set(s.tolist())) == 1 for s in seams)
+    assert {int(seams[0][0]), int(seams[1][0])} in ({1, 3}, {4, 1})
+    # more columns removed than remain: the size comes back in rounds (R23)
+    mask = np.zeros((5, 6), np.uint8)
+    mask[:, 1:5] = 1
+    out, info, _, _ = object_invariants(o, img, mask, restore=True)
+    assert info["k"] == 4 and out.shape == img.shape
+    # one row, all masked: the carve stops at one column with the last masked pixel left
+    row = rng.integers(0, 256, size=(1, 5, 3), dtype=np.uint8)
+    out, info, _, _ = object_invariants(o, row, np.ones((1, 5), np.uint8), direction=0)
+    assert info["k"] == 4 and info["left"] == 1 and out.shape == (1, 1, 3)
+    try:  # ... and a single column cannot be enlarged
+        o.remove_object(row, np.ones((1, 5), np.uint8), direction=0, restore=True)
+        raise AssertionError("restoring from one column must fail")
+    except ValueError:
+        pass
+
+
+ALL_PINS += [pin_object_hand_grid, pin_masked_seam_bruteforce, pin_object_direction, pin_object_invariants,
+             pin_object_edges]

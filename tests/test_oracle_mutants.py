@@ -69,6 +69,21 @@ MUTANTS = {
     "forward_carve_never_removes": (
         "if ((rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;\n        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);\n        if (costs_out) costs_out[k] = cost;\n    }\n    free(s);",
         "if (k < 0 && (rc = sco_remove_seam(img, H, w, C, pitch, s)) != SCO_OK) break;\n        if (seams_out) memcpy(seams_out + (size_t)k * H, s, sizeof(int32_t) * (size_t)H);\n        if (costs_out) costs_out[k] = cost;\n    }\n    free(s);"),
+    "mask_bias_added": (
+        "if (mask[(size_t)y * mpitch + x]) e[(size_t)y * W + x] -= B;",
+        "if (mask[(size_t)y * mpitch + x]) e[(size_t)y * W + x] += B;"),
+    "mask_bias_below_bound": (
+        "return (int32_t)h * 510 * C + 1;", "return (int32_t)255 * C;"),
+    "mask_not_shifted": (
+        "if ((rc = sco_remove_seam(M, h, w, 1, mp, s)) != SCO_OK) break;", ""),
+    "object_direction_inverted": (
+        "return (c1 - c0 + 1) <= (r1 - r0 + 1) ? SCO_OBJ_VERTICAL : SCO_OBJ_HORIZONTAL;",
+        "return (c1 - c0 + 1) >= (r1 - r0 + 1) ? SCO_OBJ_VERTICAL : SCO_OBJ_HORIZONTAL;"),
+    "object_loop_stops_early": (
+        "while (rc == SCO_OK && w > 1 && count_mask(M, h, w, mp) > 0)",
+        "while (rc == SCO_OK && w > 1 && count_mask(M, h, w, mp) > 1)"),
+    "object_restore_skipped_for_one_seam": (
+        "if (rc == SCO_OK && restore && k > 0) {", "if (rc == SCO_OK && restore && k > 1) {"),
     "transpose_swaps_nothing": (
         "dst[(size_t)x * dpitch + (size_t)y * C + c] = src[(size_t)y * spitch + (size_t)x * C + c];",
         "dst[(size_t)x * dpitch + (size_t)y * C + c] = src[(size_t)(y % W) * spitch + (size_t)(x % H) * C + c];"),
