@@ -266,6 +266,64 @@ sc_status sc_forward_batch_launch_copy(const sc_batch_info* info, void* ws, void
 sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream);
 
 /*
+ * Object removal with a mask (the "Object Removal" subsection of the
+ * applications section): the pixels of a binary mask get a very large
+ * negative energy, so the minimum seam runs through the object while any of it
+ * is left, and seams are removed from the image and from the mask alike until
+ * no masked pixel remains; optionally as many seams are then inserted to
+ * restore the size.  Precisely:
+ *   - masked energy: the e1 energy of the current image minus
+ *     B = h*510*C + 1 at every masked pixel (h = rows of the carved frame).  B
+ *     exceeds the e1 energy of any seam, so the minimum seam has the most
+ *     masked pixels, then the least energy, then the leftmost ties of sc_carve;
+ *   - direction: direction = SC_OBJ_AUTO takes the mask's bounding box, h_m
+ *     rows by w_m columns: vertical seams when w_m <= h_m (or the mask is
+ *     empty), horizontal seams (carved on the transpose) otherwise;
+ *   - loop: while a masked pixel is left and the frame has more than one
+ *     column, remove the minimum masked seam from the image and the mask;
+ *   - restore (restore = 1): the k removed columns come back by seam insertion
+ *     (sc_insert_seams) on the reduced frame, in rounds of at most
+ *     (current width - 1) seams; a reduced frame of one column gives SC_EINVAL.
+ * Arguments:
+ *   img, mask : H x W x C image (pitch bytes per row) and H x W mask (mpitch
+ *               bytes per row; any nonzero byte marks a pixel); not modified.
+ *   direction : SC_OBJ_AUTO, SC_OBJ_VERTICAL or SC_OBJ_HORIZONTAL.
+ *   out       : result, out_pitch >= W*C bytes per row, H rows available,
+ *               must not overlap img or mask: info->rows x info->cols pixels
+ *               (H x W when restoring; H x (W-k) for vertical seams,
+ *               (H-k) x W for horizontal ones otherwise).
+ *   info      : host struct, filled on success.
+ *   seams_out : nullable, H*W int32: seam j at seams_out[j*h + i], i < h, in
+ *               the frame that was carved (h = H vertical, W horizontal) and
+ *               the columns of the frame it was removed from.
+ *   costs_out : nullable, max(H, W) int64: the masked cost of every seam
+ *               (sum of e1 minus B times its masked pixels).
+ *   ws        : at least sc_object_workspace_bytes(H, W, C, restore) bytes,
+ *               256-byte aligned.
+ * Synchronous: the frame and the output size depend on the mask, so the call
+ * waits for the device (after the mask extent and after the carve) and
+ * returns with out complete.  One 1024-thread workgroup carves the frame.
+ * Limits: carved frame of at most 8192 columns and rows*510*C <= 8388000.
+ * Errors: SC_EINVAL, SC_ENOMEM (workspace too small), SC_EUNSUPPORTED, SC_EHIP.
+ */
+#define SC_OBJ_AUTO (-1)
+#define SC_OBJ_VERTICAL 0
+#define SC_OBJ_HORIZONTAL 1
+typedef struct {
+    int32_t direction; /* the direction used */
+    int32_t k;         /* seams removed (and inserted back when restoring) */
+    int32_t rows, cols; /* size of out */
+    int32_t left;      /* masked pixels left (0 unless the frame reached one column first) */
+    int32_t pad;
+    double carve_ms;    /* device time of the masked carve */
+    double stage_ms[3]; /* of which: DP sweep; argmin and backtrack; removal */
+} sc_object_info;
+size_t sc_object_workspace_bytes(int H, int W, int C, int restore);
+sc_status sc_remove_object(const uint8_t* img, const uint8_t* mask, int H, int W, int C, int pitch, int mpitch,
+                           int direction, int restore, uint8_t* out, int out_pitch, sc_object_info* info,
+                           int32_t* seams_out, int64_t* costs_out, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Step-wise carving for a serving loop (continuous batching).  A slot table (device memory,
  * sc_slot_table_bytes(n) bytes, caller-owned) holds one image per slot; each image keeps its own
  * workspace (sc_workspace_bytes) and stays on the device between steps.

@@ -35,6 +35,14 @@ class sc_batch_info(ctypes.Structure):
                 ("off_imgs", Z), ("off_blk", Z), ("off_teams", Z), ("off_team_imgs", Z)]
 
 
+class sc_object_info(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("k", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("left", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("carve_ms", ctypes.c_double), ("stage_ms", ctypes.c_double * 3)]
+
+
+SC_OBJ_AUTO, SC_OBJ_VERTICAL, SC_OBJ_HORIZONTAL = -1, 0, 1
+
 # name -> (restype, argtypes); exactly the functions declared in include/sc.h
 SIGNATURES = {
     "sc_last_error": (ctypes.c_char_p, []),
@@ -67,6 +75,8 @@ SIGNATURES = {
     "sc_read_times": (I, [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), I,
                           ctypes.POINTER(ctypes.c_double)]),
     "sc_read_stages": (I, [P, ctypes.POINTER(ctypes.c_uint64), I]),
+    "sc_object_workspace_bytes": (Z, [I, I, I, I]),
+    "sc_remove_object": (I, [P, P, I, I, I, I, I, I, I, P, I, ctypes.POINTER(sc_object_info), P, P, P, Z, P]),
     "sc_slot_table_bytes": (Z, [I]),
     "sc_slot_start": (I, [ctypes.POINTER(sc_job), P, Z, P, I, I, P]),
     "sc_slot_clear": (I, [P, I, I, P]),

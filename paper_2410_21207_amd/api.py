@@ -14,7 +14,7 @@ import torch
 from . import _lib
 
 __all__ = ["energy", "dp_seam", "remove_seam", "transpose", "carve", "carve_hv", "insert_seams", "workspace",
-           "BatchCarver", "variants", "read_status", "read_times", "read_stages"]
+           "BatchCarver", "variants", "read_status", "read_times", "read_stages", "remove_object"]
 
 
 def _stream(stream=None):
@@ -225,6 +225,41 @@ def carve_hv(img: torch.Tensor, target_w: int, target_h: int, record: bool = Tru
     b, hs, hc = carve(t, target_h, record=record, team=team, variant=variant, stream=stream)
     out = transpose(b, stream=stream)                     # [target_h, target_w, C]
     return out, vs, vc, hs, hc
+
+
+def remove_object(img: torch.Tensor, mask: torch.Tensor, direction: int = _lib.SC_OBJ_AUTO, restore: bool = False,
+                  record: bool = True, ws: torch.Tensor | None = None, stream=None):
+    """Remove the object under `mask` (uint8 [H, W] on the GPU, nonzero = object) from `img`
+    (sc_remove_object; synchronous).  direction: -1 = from the mask's extent, 0 = vertical seams,
+    1 = horizontal seams.  restore: insert as many seams afterwards to get the size back.
+
+    Returns (out [rows, cols, C] view of a new tensor, info dict, seams int32 [k, h] or None,
+    costs int64 [k] or None); h = H for vertical seams, W for horizontal ones.
+    """
+    H, W, C, pitch = _image(img)
+    if (not isinstance(mask, torch.Tensor) or mask.dtype != torch.uint8 or mask.dim() != 2 or not mask.is_cuda
+            or tuple(mask.shape) != (H, W) or mask.stride(1) != 1):
+        raise ValueError("mask must be a uint8 [H, W] GPU tensor with unit column stride")
+    lib = _lib.load()
+    need = lib.sc_object_workspace_bytes(H, W, C, int(bool(restore)))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, img.device)
+    out = torch.empty((H, W, C), dtype=torch.uint8, device=img.device)
+    seams = costs = None
+    if record:
+        seams = torch.empty(H * W, dtype=torch.int32, device=img.device)
+        costs = torch.empty(max(H, W), dtype=torch.int64, device=img.device)
+    info = _lib.sc_object_info()
+    _lib.call("sc_remove_object", _ptr(img), _ptr(mask), H, W, C, pitch, mask.stride(0), int(direction),
+              int(bool(restore)), _ptr(out), W * C, ctypes.byref(info), _ptr(seams), _ptr(costs), _ptr(ws),
+              ws.numel(), _stream(stream))
+    d = {"direction": info.direction, "k": info.k, "rows": info.rows, "cols": info.cols, "left": info.left,
+         "carve_ms": info.carve_ms, "stage_ms": list(info.stage_ms)}
+    h = H if info.direction == _lib.SC_OBJ_VERTICAL else W
+    if record:
+        seams = seams[: info.k * h].view(info.k, h)
+        costs = costs[: info.k]
+    return out[: info.rows, : info.cols], d, seams, costs
 
 
 def read_status(ws: torch.Tensor, n: int = 1):

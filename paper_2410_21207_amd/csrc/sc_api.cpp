@@ -821,3 +821,196 @@ extern "C" sc_status sc_forward_batch_launch_copy(const sc_batch_info* info, voi
 extern "C" sc_status sc_forward_batch_launch_carve(const sc_batch_info* info, void* ws, void* stream) {
     return fwd_batch_pass(info, ws, stream, false, true);
 }
+
+// ---------------------------------------------------------------------------------------------
+// Object removal with a mask (sec. "Object Removal"): direction from the mask's extent, masked
+// carve of the frame (the image, or its transpose for horizontal seams), optional restore by
+// seam insertion, then the result back in the caller's orientation.
+namespace {
+
+struct ObjLayout {
+    size_t ctl, desc, wk, mk, dirs, anc, seam, buf_a, buf_b, ins, ins_bytes, total;
+    int wp, mp, db;
+};
+
+// Workspace of one carved frame of h rows by w0 columns.
+ObjLayout obj_layout(int h, int w0, int C, bool restore) {
+    ObjLayout L;
+    const int P = (h + sc::kFwdPhaseRows - 1) / sc::kFwdPhaseRows;
+    L.wp = (int)sc::align_up((size_t)w0 * C, 64);
+    L.mp = (int)sc::align_up((size_t)w0, 64);
+    L.db = (int)sc::align_up((size_t)(w0 + 3) / 4, 16);
+    size_t off = 0;
+    L.ctl = off;
+    off = sc::align_up(off + sizeof(sc::ObjCtl), sc::kAlign);
+    L.desc = off;
+    off = sc::align_up(off + sizeof(sc::ObjImg), sc::kAlign);
+    L.wk = off;
+    off = sc::align_up(off + (size_t)h * L.wp + sc::kFwdSlack, sc::kAlign);
+    L.mk = off;
+    off = sc::align_up(off + (size_t)h * L.mp + sc::kFwdSlack, sc::kAlign);
+    L.dirs = off;
+    off = sc::align_up(off + (size_t)((h + 3) / 4) * L.db * 4, sc::kAlign);
+    L.anc = off;
+    off = sc::align_up(off + (size_t)P * w0, sc::kAlign);
+    L.seam = off;
+    off = sc::align_up(off + (size_t)h * 4, sc::kAlign);
+    L.buf_a = L.buf_b = L.ins = L.ins_bytes = 0;
+    if (restore && w0 >= 2) {
+        L.buf_a = off;
+        off = sc::align_up(off + (size_t)h * L.wp, sc::kAlign);
+        L.buf_b = off;
+        off = sc::align_up(off + (size_t)h * L.wp, sc::kAlign);
+        L.ins = off;
+        L.ins_bytes = sc_insert_workspace_bytes(h, w0, C, L.wp, w0 - 1);  // the largest round
+        off = sc::align_up(off + L.ins_bytes, sc::kAlign);
+    }
+    L.total = off;
+    return L;
+}
+
+sc_status check_obj_frame(int h, int w0, int C) {
+    if (w0 > sc::kFwdMaxW) return fail(SC_EUNSUPPORTED, "%d columns to carve > %d", w0, sc::kFwdMaxW);
+    if (h > sc::kFwdMaxH) return fail(SC_EUNSUPPORTED, "%d rows to carve > %d", h, sc::kFwdMaxH);
+    if ((long long)h * 510 * C > kMaxCostBound)
+        return fail(SC_EUNSUPPORTED, "rows*510*C=%lld exceeds %d (23-bit seam energy)", (long long)h * 510 * C,
+                    kMaxCostBound);
+    if ((long long)h * (long long)sc::align_up((size_t)w0 * C, 64) + (long long)sc::kFwdSlack >= (1ll << 31))
+        return fail(SC_EUNSUPPORTED, "frame of %lld bytes too large", (long long)h * w0 * C);
+    return SC_OK;
+}
+
+bool ranges_overlap(const void* a, size_t a_len, const void* b, size_t b_len) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + b_len && b0 < a0 + a_len;
+}
+
+}  // namespace
+
+extern "C" size_t sc_object_workspace_bytes(int H, int W, int C, int restore) {
+    if (H < 1 || W < 1 || C < 1 || C > 4) return 0;
+    return std::max(obj_layout(H, W, C, restore != 0).total, obj_layout(W, H, C, restore != 0).total);
+}
+
+extern "C" sc_status sc_remove_object(const uint8_t* img, const uint8_t* mask, int H, int W, int C, int pitch,
+                                      int mpitch, int direction, int restore, uint8_t* out, int out_pitch,
+                                      sc_object_info* info, int32_t* seams_out, int64_t* costs_out, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    if (H < 1 || W < 1) return fail(SC_EINVAL, "H=%d W=%d must be >= 1", H, W);
+    if (C < 1 || C > 4) return fail(SC_EINVAL, "C=%d must be in 1..4", C);
+    if ((long long)pitch < (long long)W * C) return fail(SC_EINVAL, "pitch=%d < W*C=%lld", pitch, (long long)W * C);
+    if (mpitch < W) return fail(SC_EINVAL, "mpitch=%d < W=%d", mpitch, W);
+    if ((long long)out_pitch < (long long)W * C)
+        return fail(SC_EINVAL, "out_pitch=%d < W*C=%lld", out_pitch, (long long)W * C);
+    if (direction < SC_OBJ_AUTO || direction > SC_OBJ_HORIZONTAL)
+        return fail(SC_EINVAL, "direction=%d not in {-1, 0, 1}", direction);
+    if (restore != 0 && restore != 1) return fail(SC_EINVAL, "restore=%d not 0 or 1", restore);
+    if (!img || !mask || !out || !info || !ws) return fail(SC_EINVAL, "null pointer");
+    const size_t img_len = (size_t)(H - 1) * pitch + (size_t)W * C;
+    const size_t out_len = (size_t)(H - 1) * out_pitch + (size_t)W * C;
+    if (ranges_overlap(out, out_len, img, img_len) || ranges_overlap(out, out_len, mask, (size_t)(H - 1) * mpitch + W))
+        return fail(SC_EINVAL, "out overlaps img or mask");
+    if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
+    const size_t need = sc_object_workspace_bytes(H, W, C, restore);
+    if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = static_cast<char*>(ws);
+    sc::ObjCtl* ctl = reinterpret_cast<sc::ObjCtl*>(base);  // the control block sits first in both layouts
+    sc::ObjCtl hc;
+    hipError_t e = sc::launch_obj_reset(ctl, 1, st);
+    if (e != hipSuccess) return hip_fail(e, "object reset");
+
+    // the direction (synchronous: the frame to carve depends on it)
+    int dir = direction;
+    if (dir == SC_OBJ_AUTO) {
+        e = sc::launch_mask_bbox(mask, H, W, mpitch, ctl->bbox, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "mask extent");
+        const int r0 = hc.bbox[0], r1 = hc.bbox[1], c0 = hc.bbox[2], c1 = hc.bbox[3];
+        dir = (r1 < 0 || (c1 - c0 + 1) <= (r1 - r0 + 1)) ? SC_OBJ_VERTICAL : SC_OBJ_HORIZONTAL;
+    }
+    const bool vert = dir == SC_OBJ_VERTICAL;
+    const int h = vert ? H : W, w0 = vert ? W : H;
+    sc_status s = check_obj_frame(h, w0, C);
+    if (s != SC_OK) return s;
+    const ObjLayout L = obj_layout(h, w0, C, restore != 0);
+    uint8_t* wk = reinterpret_cast<uint8_t*>(base + L.wk);
+    uint8_t* mk = reinterpret_cast<uint8_t*>(base + L.mk);
+
+    // the frame: image and mask, copied or transposed into the working buffers
+    if (vert) {
+        e = sc::launch_copy_rows(img, pitch, wk, L.wp, H, W * C, st);
+        if (e == hipSuccess) e = sc::launch_copy_rows(mask, mpitch, mk, L.mp, H, W, st);
+    } else {
+        e = sc::launch_transpose(img, H, W, C, pitch, wk, L.wp, st);
+        if (e == hipSuccess) e = sc::launch_transpose(mask, H, W, 1, mpitch, mk, L.mp, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "object frame");
+
+    // the masked carve: seams until the mask is gone (or one column is left)
+    sc::ObjImg d;
+    memset(&d, 0, sizeof(d));
+    d.wk = wk;
+    d.mk = mk;
+    d.dirs = reinterpret_cast<uint8_t*>(base + L.dirs);
+    d.anc = reinterpret_cast<int8_t*>(base + L.anc);
+    d.seam = reinterpret_cast<int32_t*>(base + L.seam);
+    d.seams_out = seams_out;
+    d.costs_out = reinterpret_cast<long long*>(costs_out);
+    d.ctl = ctl;
+    d.out = nullptr;
+    d.H = h;
+    d.W = w0;
+    d.C = C;
+    d.wp = L.wp;
+    d.mp = L.mp;
+    d.db = L.db;
+    d.max_seams = w0 - 1;
+    sc::ObjImg* desc = reinterpret_cast<sc::ObjImg*>(base + L.desc);
+    e = hipMemcpyAsync(desc, &d, sizeof(d), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = sc::launch_obj_carve(desc, 1, w0, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "object carve");
+    const int k = hc.k, left = hc.left;
+    int rw = hc.w;
+    if (k < 0 || k > w0 - 1 || rw != w0 - k) return fail(SC_EHIP, "object carve returned k=%d w=%d", k, rw);
+
+    // restore the size by seam insertion, in rounds of at most (current width - 1) seams
+    const uint8_t* cur = wk;
+    if (restore && k > 0) {
+        if (rw < 2) return fail(SC_EINVAL, "the carve left one column: nothing to insert seams into");
+        uint8_t* bufs[2] = {reinterpret_cast<uint8_t*>(base + L.buf_a), reinterpret_cast<uint8_t*>(base + L.buf_b)};
+        int nb = 0;
+        while (rw < w0) {
+            const int n = std::min(w0 - rw, rw - 1);
+            s = sc_insert_seams(cur, h, rw, C, L.wp, n, bufs[nb], L.wp, nullptr, nullptr, base + L.ins, L.ins_bytes,
+                                stream);
+            if (s != SC_OK) return s;
+            cur = bufs[nb];
+            nb ^= 1;
+            rw += n;
+        }
+    }
+
+    // the result in the caller's orientation
+    if (vert) e = sc::launch_copy_rows(cur, L.wp, out, out_pitch, h, rw * C, st);
+    else e = sc::launch_transpose(cur, h, rw, C, L.wp, out, out_pitch, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "object output");
+    int dev = 0, khz = 0;
+    double tick_ms = 0.0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        tick_ms = 1.0 / khz;
+    memset(info, 0, sizeof(*info));
+    info->direction = dir;
+    info->k = k;
+    info->rows = vert ? h : rw;
+    info->cols = vert ? rw : h;
+    info->left = left;
+    info->carve_ms = (double)(hc.t_end - hc.t_begin) * tick_ms;
+    for (int i = 0; i < 3; ++i) info->stage_ms[i] = (double)hc.t_stage[i] * tick_ms;
+    return ok();
+}

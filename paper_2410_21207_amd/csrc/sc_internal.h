@@ -103,4 +103,35 @@ constexpr int kFwdPhaseRows = 60;  // rows per backtrack phase of the forward DP
 constexpr size_t kFwdSlack = 256;
 hipError_t launch_fwd_carve(const Img* imgs, const int* order, int n, int max_w, hipStream_t st);
 
+// Object removal with a mask (one 1024-thread workgroup per image, the forward kernel's limits:
+// frame width <= kFwdMaxW, frame rows <= kFwdMaxH).  The carved frame is h = H rows by W columns
+// (the transpose of the image for horizontal seams).
+struct ObjCtl {
+    int k;        // seams removed
+    int left;     // masked pixels left when the carve stopped
+    int w;        // columns left
+    int bbox[4];  // mask bounding box: first row, last row, first column, last column
+    int pad;
+    unsigned long long t_begin, t_end;  // device clock when the carve started / ended
+    unsigned long long t_stage[3];      // device clock in: DP sweep; argmin + backtrack; removal
+};
+struct ObjImg {
+    uint8_t* wk;           // working image, H rows of wp bytes (64-byte aligned rows)
+    uint8_t* mk;           // working mask, H rows of mp bytes (nonzero = masked)
+    uint8_t* dirs;         // 2-bit direction map, rows grouped by four, db bytes per row group lane
+    int8_t* anc;           // phase ancestors when they do not fit in LDS
+    int32_t* seam;         // current seam, H
+    int32_t* seams_out;    // optional, max_seams * H
+    long long* costs_out;  // optional, max_seams
+    ObjCtl* ctl;
+    uint8_t* out;          // optional: the carved rows are copied here at the end
+    long long out_pitch;
+    int H, W, C, wp, mp, db, max_seams;
+};
+hipError_t launch_obj_reset(ObjCtl* ctl, int n, hipStream_t st);
+hipError_t launch_obj_carve(const ObjImg* imgs, int n, int max_w, hipStream_t st);
+hipError_t launch_mask_bbox(const uint8_t* mask, int H, int W, long long mpitch, int* bbox, hipStream_t st);
+hipError_t launch_copy_rows(const uint8_t* src, long long sp, uint8_t* dst, long long dp, int rows, int bytes,
+                            hipStream_t st);
+
 }  // namespace sc

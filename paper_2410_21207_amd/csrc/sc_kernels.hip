@@ -26,55 +26,11 @@
 //    with coalesced 16-byte slots, for the image and the energy plane alike;
 //    the energy is then recomputed only at the two new columns {s-1, s} of
 //    each row (the only cells whose stencil changed).
-#include <type_traits>
-#include <utility>
-
-#include "sc_internal.h"
+#include "sc_device.h"
 
 namespace sc {
 
 constexpr uint32_t QINF = 0xFFFFFF00u;  // "+infinity" key: larger than any real key, +10 cannot wrap
-
-#define GAS __attribute__((address_space(1)))
-// Every pointer reaches the kernels inside a descriptor, i.e. as a generic pointer; casting it to
-// the global address space lets the compiler emit global_* instead of flat_* memory instructions.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <class T>
-__device__ __forceinline__ GAS T* gp(T* p) {
-    return (GAS T*)p;
-}
-
-// Load of data that another workgroup of the same team may have written since this CU last read
-// it.  A relaxed device-scope atomic load is a plain load with the sc1 cache bit: it skips the
-// CU's L1 and reads the XCD's L2, where the other workgroup's stores have landed (a team always
-// runs on one XCD).  Single-workgroup carves use ordinary loads.
-template <bool COH, class T>
-__device__ __forceinline__ T ld(const T* p) {
-    if constexpr (COH)
-        return __hip_atomic_load(gp(const_cast<T*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        return *gp(p);
-}
-
-// Raw buffer descriptors (gfx9 word 3).  A raw buffer access adds a wave-uniform byte offset
-// (scalar register) to a per-lane byte offset (vector register); only the per-lane part is
-// range checked, and an access whose per-lane offset is >= the descriptor's size is dropped
-// (loads return 0, stores write nothing).
-constexpr int kBufWord3 = 0x00020000;
-constexpr uint32_t kBufDrop = 0x80000000u;  // a per-lane offset beyond any descriptor used here
-typedef unsigned int v2u __attribute__((__vector_size__(8)));
-typedef unsigned int v4u __attribute__((__vector_size__(16)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufWord3);
-}
-
-__device__ __forceinline__ uint32_t xcc_id() {
-    uint32_t v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    return v;
-}
 
 // r + 512 * (low or high 16 bits of `pair`): one v_mad_u32_u16 adds e(i,j) << 9 to a DP key
 // straight from the packed uint16 energy pair, with no separate unpack.
@@ -303,155 +259,6 @@ __device__ __forceinline__ void shift_segments_wave(uint8_t* a_lo_p, uint8_t* a_
         seg_load<U, COH>(B, fb, lane, DB);
         seg_store<U>(A, fb, lane, DA);
         seg_store<U>(B, fb, lane, DB);
-    }
-}
-
-// One segment of a one-pixel shift inside a row, as 16-byte destination slots aligned to absolute
-// addresses.  Left (R = false): destination [lo, hi) takes the bytes sh above it.  Right (R =
-// true): destination [lo + sh, hi + sh) takes the bytes of [lo, hi).  A slot's output needs its
-// own 16 bytes and one dword beyond it (above for left, below for right) that belongs to the
-// neighbouring slot; slots are numbered so that pass order visits that neighbour in the same
-// pass or a later one (left: ascending addresses, right: descending), and a pass loads before it
-// stores, so the update is hazard free.
-//
-// The row must start on a 16-byte boundary and belong to the calling wave alone while it runs:
-// a slot at either end of the destination is then written whole, with the bytes outside the
-// destination put back as loaded.
-struct SSeg {
-    uint8_t* base;  // 16-byte aligned
-    int q0, q1;     // destination bytes [base + q0, base + q1)
-    int sh;         // shift in bytes, 1..4
-    int n;          // slots
-};
-
-template <bool R>
-__device__ __forceinline__ SSeg sseg(uint8_t* lo, uint8_t* hi, int sh) {
-    SSeg g;
-    uint8_t* dlo = R ? lo + sh : lo;
-    const int off = (int)((uintptr_t)dlo & 15);
-    g.base = dlo - off;
-    g.q0 = off;
-    g.q1 = hi > lo ? off + (int)(hi - lo) : off;
-    g.sh = sh;
-    g.n = g.q1 > g.q0 ? ((g.q1 - 1) >> 4) + 1 : 0;
-    return g;
-}
-
-// W[u] holds 20 loaded bytes: left = the slot then the dword above, right = the dword below then
-// the slot.
-template <int U, bool R>
-__device__ __forceinline__ void sseg_load(const SSeg& g, int fb, int lane, uint32_t (&W)[U][5]) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) W[u][i] = 0;
-        const int f = fb + u * 64 + lane;
-        if (f < g.n) {
-            const int so = (R ? g.n - 1 - f : f) << 4;
-            const uint8_t* sp = g.base + so;
-            const uint64_t v0 = *gp(reinterpret_cast<const uint64_t*>(sp));
-            const uint64_t v1 = *gp(reinterpret_cast<const uint64_t*>(sp) + 1);
-            constexpr int k = R ? 1 : 0;
-            W[u][k + 0] = (uint32_t)v0; W[u][k + 1] = (uint32_t)(v0 >> 32);
-            W[u][k + 2] = (uint32_t)v1; W[u][k + 3] = (uint32_t)(v1 >> 32);
-            if (R) {
-                if (so > g.q0 - g.sh) W[u][0] = *gp(reinterpret_cast<const uint32_t*>(sp - 4));
-            } else {
-                if (so + 16 - g.sh < g.q1) W[u][4] = *gp(reinterpret_cast<const uint32_t*>(sp + 16));
-            }
-        }
-    }
-}
-
-template <int U, bool R>
-__device__ __forceinline__ void sseg_store(const SSeg& g, int fb, int lane, const uint32_t (&W)[U][5]) {
-    const int a = R ? 4 - g.sh : g.sh;  // byte offset of the output inside the 20 bytes
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int f = fb + u * 64 + lane;
-        if (f >= g.n) continue;
-        const int so = (R ? g.n - 1 - f : f) << 4;
-        uint32_t o[4];
-        if (a == 4) {
-            o[0] = W[u][1]; o[1] = W[u][2]; o[2] = W[u][3]; o[3] = W[u][4];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbyte(W[u][i + 1], W[u][i], (uint32_t)a);
-        }
-        if (so < g.q0 || so + 16 > g.q1) {
-            // an end slot: bytes outside the destination keep the values the pass loaded
-            const int c0 = min(max(g.q0 - so, 0), 16), c1 = min(max(g.q1 - so, 0), 16);
-            const uint32_t m16 = ((1u << c1) - 1u) & ~((1u << c0) - 1u);  // bit k = byte k of the slot
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t bm = ((((m16 >> (4 * i)) & 15u) * 0x00204081u) & 0x01010101u) * 0xffu;
-                const uint32_t cur = R ? W[u][i + 1] : W[u][i];
-                o[i] = (o[i] & bm) | (cur & ~bm);
-            }
-        }
-        *gp(reinterpret_cast<u32x4*>(g.base + so)) = u32x4{o[0], o[1], o[2], o[3]};
-    }
-}
-
-// Two rows' shifts (image and energy segments of row a, then of row b, directions RA and RB)
-// moved together: every pass issues the loads of all four segments before any store, so the
-// rows share each memory round trip.  The segments must not overlap each other's bytes.
-template <int U, bool RA, bool RB>
-__device__ __forceinline__ void shift_rows2_wave(const SSeg& a0, const SSeg& a1, const SSeg& b0, const SSeg& b1,
-                                                 int lane) {
-    const int n = max(max(a0.n, a1.n), max(b0.n, b1.n));
-#pragma unroll 1
-    for (int fb = 0; fb < n; fb += 64 * U) {
-        uint32_t W0[U][5], W1[U][5], W2[U][5], W3[U][5];
-        sseg_load<U, RA>(a0, fb, lane, W0);
-        sseg_load<U, RA>(a1, fb, lane, W1);
-        sseg_load<U, RB>(b0, fb, lane, W2);
-        sseg_load<U, RB>(b1, fb, lane, W3);
-        sseg_store<U, RA>(a0, fb, lane, W0);
-        sseg_store<U, RA>(a1, fb, lane, W1);
-        sseg_store<U, RB>(b0, fb, lane, W2);
-        sseg_store<U, RB>(b1, fb, lane, W3);
-    }
-}
-
-// dst bytes [dst, dst + n) take the bytes of [src, src + n), one wave; the buffers do not overlap.
-// Dword-granular on the destination; bytes of a destination dword outside [dst, dst + n) are not
-// written (they may belong to a neighbouring row).  Source dwords may be read a few bytes beyond
-// either end of the source range.
-__device__ __forceinline__ void copy_bytes_wave(uint8_t* dst, const uint8_t* src, int n, int lane) {
-    if (n <= 0) return;
-    const int off = (int)((uintptr_t)dst & 3);
-    uint8_t* const base = dst - off;  // dword-aligned; destination dword j covers base + 4j
-    const int nd = ((off + n - 1) >> 2) + 1;
-    const uintptr_t s0 = (uintptr_t)src - (uintptr_t)off;  // source byte of base + x is s0 + x
-#pragma unroll 1
-    for (int jb = 0; jb < nd; jb += 64 * 4) {
-        uint32_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = jb + u * 64 + lane;
-            v[u] = 0;
-            if (j < nd) {
-                const uintptr_t sa = s0 + 4 * (uintptr_t)j;
-                const uint32_t* sp = reinterpret_cast<const uint32_t*>(sa & ~(uintptr_t)3);
-                const uint32_t lo = *gp(sp);
-                const uint32_t hi = (sa & 3) ? *gp(sp + 1) : 0u;
-                v[u] = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(sa & 3));
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int j = jb + u * 64 + lane;
-            if (j >= nd) continue;
-            uint8_t* dp = base + 4 * j;
-            if (dp >= dst && dp + 4 <= dst + n) {
-                *gp(reinterpret_cast<uint32_t*>(dp)) = v[u];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (dp + k >= dst && dp + k < dst + n) *gp(dp + k) = (uint8_t)(v[u] >> (8 * k));
-            }
-        }
     }
 }
 
@@ -1225,16 +1032,6 @@ __global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint
     }
 }
 
-// Calls f(std::integral_constant<int, 0>{}) ... f(std::integral_constant<int, N-1>{}) in order.
-template <class F, int... I>
-__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    static_for_seq(f, std::make_integer_sequence<int, N>{});
-}
-
 // ----------------------------------------------------------------------------------------------
 // Forward energy (sec. "Forward Energy Calculation", the standard definition with no per-pixel
 // term): the DP cost of removing pixel (i,j) is the difference of the pixel pairs its removal
@@ -1277,57 +1074,12 @@ struct Smem {
     uint8_t anc[ANC_LDS];
 };
 
-__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t o;
-    asm("v_min3_u32 %0, %1, %2, %3" : "=v"(o) : "v"(a), "v"(b), "v"(c));
-    return o;
-}
-
-// kk + (cu << 9) - 127 * tag - 1 with tag = bits 7-8 of kk: drops the tag, adds CU to M and moves
-// the ancestor offset by tag - 1.
-__device__ __forceinline__ uint32_t next_state(uint32_t kk, uint32_t cu) {
-    const uint32_t tag = (kk >> 7) & 3u;
-    uint32_t o;
-    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(o) : "v"(tag), "s"(-127), "v"(kk + (cu << 9) - 1u));
-    return o;
-}
-
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <int C, int CPL>
-struct Carver {
-    // A thread reads the dwords covering columns j0-1 .. j0+CPL of a row: they start at byte
-    // j0*C - 4 (j0*C is a multiple of 4 because CPL is), where column j0-1 sits at byte LEAD.
-    static constexpr int LEAD = (4 - C % 4) % 4;
-    static constexpr int NDW = (LEAD + (CPL + 2) * C + 3) / 4;
-    static constexpr uint32_t PMASK = C == 4 ? 0xFFFFFFFFu : (1u << (8 * C)) - 1u;
-    static_assert(CPL % 4 == 0, "a thread's directions fill whole bytes");
-
-    // vl: byte offset of the dword left of column j0 (it holds only column j0-1); v0: of column j0.
-    // Either is kBufDrop where nothing may be read (the load then returns 0).
-    static __device__ __forceinline__ void load_row(uint32_t (&v)[NDW], __amdgpu_buffer_rsrc_t r, uint32_t vl,
-                                                    uint32_t v0, uint32_t soff) {
-        v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)vl, (int)soff, 0);
-#pragma unroll
-        for (int q = 1; q < NDW; ++q) v[q] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(v0 + 4u * (q - 1)), (int)soff, 0);
-    }
-
-    // pixel k (column j0-1+k) of a loaded row, channels packed in the low bytes
-    static __device__ __forceinline__ void pixels(const uint32_t (&v)[NDW], uint32_t (&p)[CPL + 2]) {
-#pragma unroll
-        for (int k = 0; k < CPL + 2; ++k) {
-            const int o = LEAD + C * k, q = o >> 2, r = o & 3;
-            uint32_t x;
-            if (r == 0) x = v[q];
-            else if (r + C <= 4) x = v[q] >> (8 * r);
-            else x = __builtin_amdgcn_alignbyte(v[q + 1], v[q], (uint32_t)r);
-            p[k] = x & PMASK;
-        }
-    }
+struct Carver : PixRow<C, CPL> {
+    using Row = PixRow<C, CPL>;
+    using Row::load_row;
+    using Row::pixels;
+    static constexpr int NDW = Row::NDW;
 
     static __device__ __forceinline__ void carve(const Img& d, Smem& sm) {
         const int t = threadIdx.x, lane = t & 63, wv = t >> 6;

@@ -15,6 +15,8 @@ of which is available; the distributions below stand in for them:
   width (the batched configuration).
 * ``serving_requests``: Poisson arrivals of blob images with log-uniform sides
   (the serving configuration).
+* ``object_mask``: a filled axis-aligned ellipse (the object of the object-removal
+  application), optionally with a few stray pixels.
 """
 from __future__ import annotations
 
@@ -24,7 +26,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = ["uniform_image", "blob_image", "batch_jobs", "serving_requests", "Job", "Request",
-           "canvas_crop"]
+           "canvas_crop", "object_mask", "ellipse_mask"]
 
 
 def uniform_image(h: int, w: int, c: int = 3, seed: int = 0) -> np.ndarray:
@@ -158,3 +160,24 @@ def resized(img: np.ndarray, n: int, m: int | None = None) -> np.ndarray:
     ys = (np.arange(n) * H) // n
     xs = (np.arange(m) * W) // m
     return np.ascontiguousarray(img[ys][:, xs])
+
+
+def ellipse_mask(h: int, w: int, cy: float, cx: float, ry: float, rx: float) -> np.ndarray:
+    """uint8 [h, w] mask, 1 inside the axis-aligned ellipse ((y-cy)/ry)^2 + ((x-cx)/rx)^2 <= 1."""
+    y = (np.arange(h, dtype=np.float64)[:, None] - cy) / max(ry, 1e-9)
+    x = (np.arange(w, dtype=np.float64)[None, :] - cx) / max(rx, 1e-9)
+    return ((y * y + x * x) <= 1.0).astype(np.uint8)
+
+
+def object_mask(h: int, w: int, seed: int, size=(0.05, 0.25), stray: int = 0) -> np.ndarray:
+    """A seeded object: a filled ellipse with semi-axes uniform in size * (h, w), centred uniformly
+    where it fits, plus `stray` isolated masked pixels anywhere (values 1..255)."""
+    rng = np.random.default_rng(seed)
+    ry = max(0.5, rng.uniform(*size) * h)
+    rx = max(0.5, rng.uniform(*size) * w)
+    cy = rng.uniform(min(ry, h / 2), max(h - ry, h / 2))
+    cx = rng.uniform(min(rx, w / 2), max(w - rx, w / 2))
+    m = ellipse_mask(h, w, cy, cx, ry, rx)
+    for _ in range(stray):
+        m[int(rng.integers(0, h)), int(rng.integers(0, w))] = int(rng.integers(1, 256))
+    return m
