@@ -154,6 +154,27 @@ sc_status sc_carve(uint8_t* img, int H, int W, int C, int target_w, int pitch, i
                    void* ws, size_t ws_bytes, void* stream, const uint8_t* src, const sc_tune* tune);
 
 /*
+ * sc_carve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same carve, arguments and results as sc_carve, with its scratch in a fixed
+ * array of SC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends, instead of a caller's workspace.  The call
+ * allocates nothing (no hipMalloc, no library allocation).
+ *   status_out : nullable device uint32, receives the device-side status of
+ *                the carve (0 = fine, nonzero = the flags of sc_read_status:
+ *                the results are then invalid).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * contents (the carve clears what must start at zero): calls that overlap on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller.  An image whose sc_workspace_bytes(H, W, C) exceeds
+ * SC_NOALLOC_SCRATCH_BYTES (about 3840 x 2160 x 3 fits) returns SC_ENOMEM.
+ */
+#define SC_NOALLOC_SCRATCH_BYTES (64u << 20)
+sc_status sc_carve_noalloc(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out,
+                           int64_t* costs_out, uint32_t* status_out, void* stream, const uint8_t* src,
+                           const sc_tune* tune);
+
+/*
  * Seam insertion (the "Image Enlargement" subsection of the applications
  * section): widen img by k columns.  The k minimum seams are found by removal
  * on a copy, exactly as sc_carve(img -> W - k) removes them; img itself is not

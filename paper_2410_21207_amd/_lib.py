@@ -23,6 +23,7 @@ class sc_tune(ctypes.Structure):
 
 SC_TUNE_NO_MINSIDE = 1
 SC_TUNE_XCD_SHIFT = 8
+SC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class sc_job(ctypes.Structure):
@@ -55,6 +56,7 @@ SIGNATURES = {
     "sc_variant_count": (I, []),
     "sc_variant_name": (ctypes.c_char_p, [I]),
     "sc_carve": (I, [P, I, I, I, I, I, P, P, P, Z, P, P, ctypes.POINTER(sc_tune)]),
+    "sc_carve_noalloc": (I, [P, I, I, I, I, I, P, P, P, P, P, ctypes.POINTER(sc_tune)]),
     "sc_insert_workspace_bytes": (Z, [I, I, I, I, I]),
     "sc_insert_seams": (I, [P, I, I, I, I, I, P, I, P, ctypes.POINTER(sc_tune), P, Z, P]),
     "sc_batch_workspace_bytes": (Z, [ctypes.POINTER(sc_job), I]),

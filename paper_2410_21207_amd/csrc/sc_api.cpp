@@ -234,6 +234,34 @@ sc_status sc_carve(uint8_t* img, int H, int W, int C, int target_w, int pitch, i
     return ok();
 }
 
+// sc_carve with its scratch in the library's fixed per-GPU device array instead of a caller's
+// workspace: same validation, same kernels, no allocation of any kind.
+sc_status sc_carve_noalloc(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out,
+                           int64_t* costs_out, uint32_t* status_out, void* stream, const uint8_t* src,
+                           const sc_tune* tune) {
+    static_assert(sc::kNoAllocScratchBytes == (size_t)SC_NOALLOC_SCRATCH_BYTES, "scratch size");
+    sc_status s = check_image(H, W, C, pitch);
+    if (s != SC_OK) return s;
+    const size_t need = sc_workspace_bytes(H, W, C);
+    if (need > sc::kNoAllocScratchBytes)
+        return fail(SC_ENOMEM, "a %dx%dx%d image needs %zu bytes of scratch; the fixed scratch holds %zu", H, W, C,
+                    need, sc::kNoAllocScratchBytes);
+    if (!img) return fail(SC_EINVAL, "null pointer");
+    if (target_w < 1 || target_w > W) return fail(SC_EINVAL, "target_w=%d not in [1, W=%d]", target_w, W);
+    void* ws = nullptr;
+    hipError_t e = sc::noalloc_scratch(&ws);
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    s = sc_carve(img, H, W, C, target_w, pitch, seams_out, costs_out, ws, sc::kNoAllocScratchBytes, stream, src,
+                 tune);
+    if (s != SC_OK) return s;
+    if (status_out) {
+        const sc::Ctl* ctl = reinterpret_cast<const sc::Ctl*>(static_cast<const char*>(ws) + sizeof(WsHead));
+        e = sc::launch_copy_status(&ctl->status, status_out, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "status copy");
+    }
+    return ok();
+}
+
 namespace {
 // Workspace of sc_insert_seams: the carve's own workspace, a scratch image the carve writes, the
 // seams in removal coordinates and in original columns, and the per-row Fenwick trees.

@@ -134,4 +134,11 @@ hipError_t launch_mask_bbox(const uint8_t* mask, int H, int W, long long mpitch,
 hipError_t launch_copy_rows(const uint8_t* src, long long sp, uint8_t* dst, long long dp, int rows, int bytes,
                             hipStream_t st);
 
+// Allocation-free carve: the fixed device scratch of the current GPU (looked up once per device)
+// and a one-thread copy of an image's status word to a caller's device word.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;  // = SC_NOALLOC_SCRATCH_BYTES of sc.h
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch(void** ptr);
+hipError_t launch_copy_status(const unsigned* src, uint32_t* dst, hipStream_t st);
+
 }  // namespace sc

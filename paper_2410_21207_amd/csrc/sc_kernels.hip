@@ -26,6 +26,8 @@
 //    with coalesced 16-byte slots, for the image and the energy plane alike;
 //    the energy is then recomputed only at the two new columns {s-1, s} of
 //    each row (the only cells whose stencil changed).
+#include <mutex>
+
 #include "sc_device.h"
 
 namespace sc {
@@ -1480,6 +1482,39 @@ hipError_t launch_transpose(const uint8_t* src, int H, int W, int C, long long s
         case 4: hipLaunchKernelGGL(transpose_kernel<4>, grid, dim3(256), 0, st, src, H, W, sp, dst, dp); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------------------------
+// Fixed scratch of the allocation-free carve (sc_carve_noalloc): a file-scope device array, one
+// copy per GPU, held until the process ends.  In host code the array's name is only a host-side
+// stand-in for it; the device address of each GPU's copy is looked up once per device with that
+// device current and kept, and only that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** ptr) {
+    static std::mutex mu;
+    static void* addr[kNoAllocMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+__global__ void copy_status_kernel(const unsigned* __restrict__ src, uint32_t* __restrict__ dst) { *dst = *src; }
+
+hipError_t launch_copy_status(const unsigned* src, uint32_t* dst, hipStream_t st) {
+    hipLaunchKernelGGL(copy_status_kernel, dim3(1), dim3(1), 0, st, src, dst);
     return hipGetLastError();
 }
 

@@ -105,6 +105,19 @@ def test_carve_validation(lib):
     assert carve(lib, FAKE, 10, 10, 3, 5, 30, ws, 1 << 30, ctypes.byref(big)) == _lib.SC_EUNSUPPORTED
 
 
+def test_noalloc_validation(lib):
+    """sc_carve_noalloc rejects bad shapes and images larger than its fixed scratch before any
+    device call."""
+    big = (4096, 4096, 3)
+    assert lib.sc_workspace_bytes(*big) > _lib.SC_NOALLOC_SCRATCH_BYTES
+    assert lib.sc_carve_noalloc(FAKE, *big, 4000, 4096 * 3, None, None, None, None, None, None) == _lib.SC_ENOMEM
+    assert b"fixed scratch" in lib.sc_last_error()
+    assert lib.sc_carve_noalloc(FAKE, 0, 10, 3, 5, 30, None, None, None, None, None, None) == _lib.SC_EINVAL
+    assert lib.sc_carve_noalloc(FAKE, 10, 10, 3, 11, 30, None, None, None, None, None, None) == _lib.SC_EINVAL
+    assert lib.sc_carve_noalloc(None, 10, 10, 3, 5, 30, None, None, None, None, None, None) == _lib.SC_EINVAL
+    assert lib.sc_workspace_bytes(2160, 3840, 3) <= _lib.SC_NOALLOC_SCRATCH_BYTES  # 3840x2160 RGB fits
+
+
 def test_dp_and_remove_and_transpose_validation(lib):
     assert lib.sc_dp_seam(FAKE, 4, 4, FAKE, FAKE, FAKE, 8, None, None) == _lib.SC_ENOMEM
     assert lib.sc_dp_seam(None, 4, 4, FAKE, FAKE, FAKE, 1 << 20, None, None) == _lib.SC_EINVAL
