@@ -58,17 +58,25 @@ constexpr size_t kWsHeadBytes = 256;        // header, then one Ctl per image
 constexpr size_t kWsImgOffset = 64;         // single-image workspaces keep their descriptor here
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Kernel variants: columns per lane, rows per DP phase, threads per workgroup.
+// Kernel variants: columns per lane, rows per DP phase, threads per workgroup.  X(id, cpl, kr,
+// threads) for every compiled variant of the carve kernel; the launchers switch over the same list.
+#define SC_VARIANTS(X)                                                                                      \
+    X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) \
+    X(6, 4, 48, 256) X(7, 4, 56, 512) X(8, 4, 56, 256)
+
 struct Variant {
     int cpl, kr, threads;
     const char* name;
 };
+#define SC_VARIANT_ROW(id, c, k, t) {c, k, t, "cpl" #c "_k" #k "_t" #t},
+inline constexpr Variant kVariants[] = {SC_VARIANTS(SC_VARIANT_ROW)};
+#undef SC_VARIANT_ROW
+inline int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+inline const Variant& variant(int v) { return kVariants[v]; }
+inline int default_variant() { return 7; }  // cpl4_k56_t512
+inline int team_variant() { return 7; }
 
 Layout layout_for(int H, int W, int C, int variant_kr_min);
-int variant_count();
-const Variant& variant(int v);
-int default_variant();
-int team_variant();
 constexpr int kLdsExchangeMaxW = 4096;  // single-workgroup carves keep the phase exchange row in LDS up to this width
 
 // Launchers (sc_kernels.hip).  Return hipSuccess or the launch error.

@@ -1338,27 +1338,7 @@ __global__ __launch_bounds__(fwd::NT, 1) void fwd_carve_kernel(const Img* __rest
 }
 
 // ----------------------------------------------------------------------------------------------
-// Variant table and launchers.
-static const Variant kVariants[] = {
-    {4, 32, 256, "cpl4_k32_t256"},
-    {4, 32, 512, "cpl4_k32_t512"},
-    {4, 32, 1024, "cpl4_k32_t1024"},
-    {8, 32, 512, "cpl8_k32_t512"},
-    {8, 32, 1024, "cpl8_k32_t1024"},
-    {4, 48, 512, "cpl4_k48_t512"},
-    {4, 48, 256, "cpl4_k48_t256"},
-    {4, 56, 512, "cpl4_k56_t512"},
-    {4, 56, 256, "cpl4_k56_t256"},
-};
-int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
-const Variant& variant(int v) { return kVariants[v]; }
-int default_variant() { return 7; }
-int team_variant() { return 7; }
-
-#define SC_VARIANTS(X) \
-    X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) X(6, 4, 48, 256) \
-    X(7, 4, 56, 512) X(8, 4, 56, 256)
-
+// Launchers of the carve kernel variants (the table of shapes: SC_VARIANTS in sc_internal.h).
 hipError_t launch_carve_single(const Img& d, int v, int G, int xcd, hipStream_t st) {
     switch (v) {
 #define X(id, c, k, t) \
