@@ -33,7 +33,7 @@ METRIC = "pixel-seams removed/sec + HBM GB/s %peak; p50/p99 carve latency, batch
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "carve_batch_c4_traffic.json")
 FWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_carve_batch_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_21207_amd", "csrc", f)
-                  for f in ("sc_kernels.hip", "sc_internal.h")]
+                  for f in ("sc_kernels.hip", "sc_device.h", "sc_internal.h")]
 
 
 def log(*a):
@@ -103,7 +103,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU oracle sample: about this many seconds of work per host core (the batch's "
                          "critical image is always in the sample)")
-    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward", "forward1080p"],
+    ap.add_argument("--workload", choices=["batch", "1080p", "4k", "insert", "sweep", "forward", "forward1080p",
+                                           "object"],
                     default="batch",
                     help="batch (default): the batched configuration; 1080p / 4k: one image on the plain "
                          "per-image path (1920x1080, 480 seams; 3840x2160, 960 vertical then 540 horizontal); "
@@ -138,6 +139,9 @@ def main():
         return
     if args.workload == "forward1080p":
         forward_single(args, dev)
+        return
+    if args.workload == "object":
+        object_removal(args, dev)
         return
     if args.workload != "batch":
         single(args, dev)
@@ -620,6 +624,85 @@ def forward_single(args, dev):
                       "config": {"workload": "forward-energy carve: one 1920x1080 RGB uint8 blob+noise image "
                                              "(seed 1) to 1440 columns", "pixel_seams": ps},
                       "gpu_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 3)}), flush=True)
+
+
+def object_byte_model(h: int, w0: int, C: int, seams: np.ndarray) -> int:
+    """Algorithmic HBM bytes of the masked carve of an h-row frame from its recorded seams.
+
+    Per seam on a frame of current width w: the DP reads the pixels and the mask byte of every
+    cell and writes a 2-bit direction ((C + 1.25) bytes per cell; the energy is computed from the
+    pixels it reads); the removal moves the pixels and mask bytes right of the seam one column
+    left (read and write, 2 * (C + 1) bytes each)."""
+    total = 0
+    for j in range(seams.shape[0]):
+        w = w0 - j
+        total += int(h * w * (C + 1.25)) + 2 * (C + 1) * int(np.sum(w - 1 - seams[j].astype(np.int64)))
+    return total
+
+
+def object_removal(args, dev):
+    """Object removal with a mask: one 1920x1080 RGB blob+noise image (seed 1) with a filled
+    elliptical object of semi-axes 100 x 200 px at the centre, removed by masked vertical seams
+    and the size restored by seam insertion."""
+    import torch
+
+    import synth
+    from paper_2410_21207_amd import api
+
+    H, W, C = 1080, 1920, 3
+    img_np = synth.blob_image(H, W, C, seed=1)
+    mask_np = synth.ellipse_mask(H, W, 540, 960, 200, 100)
+    img = torch.from_numpy(img_np).to(dev)
+    mask = torch.from_numpy(mask_np).to(dev)
+    lib = api._lib.load()
+    ws = api.workspace(lib.sc_object_workspace_bytes(H, W, C, 1), dev)
+    for _ in range(args.warmup):
+        api.remove_object(img, mask, restore=True, record=False, ws=ws)
+    torch.cuda.synchronize()
+    walls, carve_ms, stages = [], [], []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        out, info, _, _ = api.remove_object(img, mask, restore=True, record=False, ws=ws)  # synchronous
+        walls.append(time.perf_counter() - t0)
+        carve_ms.append(info["carve_ms"])
+        stages.append(info["stage_ms"])
+    out, info, seams, costs = api.remove_object(img, mask, restore=True, ws=ws)
+    seams = seams.cpu().numpy()
+    k = info["k"]
+    h, w0 = (H, W) if info["direction"] == 0 else (W, H)
+    ps = h * sum(w0 - j for j in range(k))  # pixel-seams of the masked carve
+    model = object_byte_model(h, w0, C, seams)
+    cms = float(np.median(carve_ms))
+    wall = float(np.median(walls))
+    res = {"metric": METRIC, "value": round(ps / wall, 1), "unit": "pixel-seams/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1000.0, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic",
+           "config": {"workload": "object removal: one 1920x1080 RGB uint8 blob+noise image (seed 1), filled "
+                                  "ellipse mask of semi-axes 100x200 px at the centre, masked seams until the "
+                                  "object is gone, then the size restored by seam insertion",
+                      "direction": info["direction"], "seams": k, "pixel_seams": ps},
+           "roofline": {"bound": "hbm", "achieved": round(model / (cms / 1000.0) / 1e9, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(model / (cms / 1000.0) / 8e12, 4), "traffic": None,
+                        "kernel": "obj_carve_kernel", "model_bytes_per_launch": model,
+                        "kernel_ms": round(cms, 3)},
+           "stages_ms": {"dp": round(float(np.median([s[0] for s in stages])), 3),
+                         "argmin_backtrack": round(float(np.median([s[1] for s in stages])), 3),
+                         "removal": round(float(np.median([s[2] for s in stages])), 3)},
+           "carve_pixel_seams_per_s": round(ps / (cms / 1000.0), 1),
+           "restore_and_rest_ms": round(wall * 1000.0 - cms, 3)}
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        o_out, o_info, o_seams, o_costs = oracle.remove_object(img_np, mask_np, -1, True)
+        ct = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(ps / ct, 1), "unit": "pixel-seams/s (whole call incl. restore)",
+                               "cores": 1, "kind": "oracle", "sample": "the whole workload, one host thread",
+                               "seconds": round(ct, 2),
+                               "matches_gpu": bool(np.array_equal(o_seams, seams) and
+                                                   np.array_equal(o_costs, costs.cpu().numpy()) and
+                                                   np.array_equal(o_out, out.cpu().numpy()))}
+    print(json.dumps(res), flush=True)
 
 
 def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False, must=()):
