@@ -116,42 +116,132 @@ __device__ __forceinline__ void clear_exchange(const Img& d) {
     for (int x = threadIdx.x; x < 2 * d.xw; x += blockDim.x) *gp(d.xq + x) = 0u;
 }
 
-// The carve works on the copy in wk; img receives the result at the end (a carve that removes
-// nothing copies src into img here).
-__device__ void prepare_rows(const Img& d, int row_begin, int row_step) {
-    const uint8_t* srcimg = d.src ? d.src : d.img;
+// The energy pass (a1) and the copy into the working image.  The carve works on the copy in wk;
+// img receives the result at the end (a carve that removes nothing copies src into img here).
+//
+// A workgroup sweeps one tile: a strip of 1024 columns (4 per thread) down kTileRows rows.  Each
+// source row is read once per tile, as the aligned dwords covering the thread's 4 pixels and one
+// pixel on each side, realigned to the row start with v_alignbyte (rows may start anywhere); the
+// rows above and below stay in registers as the tile moves down.  The energy goes out as one
+// 8-byte store of 4 uint16 per thread, the pixels as C dword stores into the 64-byte aligned rows
+// of wk.
+constexpr int kTileRows = 32;
+constexpr int kTileCols = 1024;  // 256 threads x 4 pixels
+
+template <int C>
+struct SrcRow {
+    static constexpr int ND = C + 3;   // dwords loaded per thread
+    static constexpr uint32_t PMASK = C == 4 ? 0xFFFFFFFFu : (1u << (8 * C)) - 1u;
+    uint32_t r[C + 2];                 // row bytes [x0*C - 4, x0*C + 4*C + 4), dword aligned to the row
+
+    // Row y of the image (pitch bytes per row, W*C bytes used): the thread's pixels start at x0.
+    __device__ __forceinline__ void load(const uint8_t* img, long long pitch, int W, int y, int x0) {
+        const uint8_t* row = img + (long long)y * pitch;
+        const uint32_t sh = (uint32_t)((uintptr_t)row & 3u);
+        // the descriptor covers the whole dwords holding the row's bytes (a dword-aligned dword that
+        // holds an image byte lies inside the image's allocation); dwords outside are dropped (read
+        // as 0), and only clamped neighbours would use them
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(row - sh, (sh + (uint32_t)(W * C) + 3u) & ~3u);
+        // per-lane offsets never wrap: the dword left of column x0 has an offset of its own (dropped
+        // at x0 = 0), the others count up from column x0 (an immediate offset may be folded in)
+        const uint32_t v0 = x0 < W ? (uint32_t)(x0 * C) : kBufDrop;
+        const uint32_t vl = x0 < W && x0 > 0 ? (uint32_t)(x0 * C - 4) : kBufDrop;
+        uint32_t d[ND];
+        d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vl, 0, 0);
+#pragma unroll
+        for (int m = 1; m < ND; ++m) d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(v0 + 4u * (m - 1)), 0, 0);
+#pragma unroll
+        for (int m = 0; m < C + 2; ++m) r[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
+    }
+    // pixel p of the thread (p = -1 .. 4), channels packed in the low bytes
+    __device__ __forceinline__ uint32_t px(int p) const {
+        const int o = 4 + p * C, q = o >> 2, b = o & 3;
+        const uint32_t v = b == 0 ? r[q] : __builtin_amdgcn_alignbyte(r[q + 1], r[q], (uint32_t)b);
+        return v & PMASK;
+    }
+};
+
+template <int C>
+__device__ void prepare_tile(const Img& d, const uint8_t* srcimg, int y0, int y1, int xs) {
+    const int t = threadIdx.x, x0 = xs + 4 * t, H = d.H, W = d.W;
+    const bool act = x0 < W;
     const bool identity = d.src && d.target_w == d.W;
-    if (row_begin == 0) {
+    SrcRow<C> up, cur, dn;
+    up.load(srcimg, d.pitch, W, max(y0 - 1, 0), x0);
+    cur.load(srcimg, d.pitch, W, y0, x0);
+    dn.load(srcimg, d.pitch, W, min(y0 + 1, H - 1), x0);
+#pragma unroll 1
+    for (int y = y0; y < y1; ++y) {
+        SrcRow<C> nx;
+        if (y + 1 < y1) nx.load(srcimg, d.pitch, W, min(y + 2, H - 1), x0);
+        if (act) {
+            if (d.e) {
+                uint32_t e[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int x = x0 + p;
+                    const uint32_t l = x > 0 ? cur.px(p - 1) : cur.px(p);
+                    const uint32_t rr = x + 1 < W ? cur.px(p + 1) : cur.px(p);
+                    e[p] = __builtin_amdgcn_sad_u8(up.px(p), dn.px(p), __builtin_amdgcn_sad_u8(l, rr, 0u));
+                }
+                uint16_t* er = d.e + (long long)y * d.ep + x0;
+                if (x0 + 3 < W) {
+                    *gp(reinterpret_cast<v2u*>(er)) = v2u{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+                } else {
+#pragma unroll
+                    for (int p = 0; p < 4; ++p)
+                        if (x0 + p < W) *gp(er + p) = (uint16_t)e[p];
+                }
+            }
+            uint32_t* wr = reinterpret_cast<uint32_t*>(d.wk + (long long)y * d.wp + (long long)x0 * C);
+#pragma unroll
+            for (int m = 0; m < C; ++m)
+                if (x0 * C + 4 * m < W * C) *gp(wr + m) = cur.r[m + 1];
+            if (identity) {
+                uint8_t* o = d.img + (long long)y * d.pitch + (long long)x0 * C;
+#pragma unroll
+                for (int b = 0; b < 4 * C; ++b)
+                    if (x0 * C + b < W * C) *gp(o + b) = (uint8_t)(cur.r[1 + (b >> 2)] >> (8 * (b & 3)));
+            }
+        }
+        up = cur;
+        cur = dn;
+        dn = nx;
+    }
+}
+
+// Tiles tile0, tile0 + tstep, ... of one image (tiles numbered strip-major within row chunks);
+// tile 0 also resets the control words and clears the exchange rows.
+__device__ void prepare_image(const Img& d, int tile0, int tstep) {
+    const uint8_t* srcimg = d.src ? d.src : d.img;
+    if (tile0 == 0) {
         if (threadIdx.x == 0) reset_ctl(d);
         clear_exchange(d);
     }
-    for (int y = row_begin; y < d.H; y += row_step) {
-        if (threadIdx.x == 0) *gp(d.ro + y) = 0;
-        uint16_t* er = d.e ? d.e + (long long)y * d.ep : nullptr;  // no energy plane: forward energy
-        const uint8_t* s = srcimg + (long long)y * d.pitch;
-        uint8_t* wr = d.wk + (long long)y * d.wp;
-        uint8_t* o = d.img + (long long)y * d.pitch;
-        for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
-            if (d.e) *gp(er + x) = (uint16_t)energy_at(srcimg, d.pitch, d.H, d.W, d.C, y, x);
-            for (int c = 0; c < d.C; ++c) {
-                const uint8_t v = *gp(s + x * d.C + c);
-                *gp(wr + x * d.C + c) = v;
-                if (identity) *gp(o + x * d.C + c) = v;
-            }
+    const int ns = (d.W + kTileCols - 1) / kTileCols, nc = (d.H + kTileRows - 1) / kTileRows;
+    for (int tile = tile0; tile < ns * nc; tile += tstep) {
+        const int strip = tile % ns, chunk = tile / ns;
+        const int y0 = chunk * kTileRows, y1 = min(d.H, y0 + kTileRows);
+        if (strip == 0 && (int)threadIdx.x < y1 - y0) *gp(d.ro + y0 + threadIdx.x) = 0;
+        switch (d.C) {
+            case 1: prepare_tile<1>(d, srcimg, y0, y1, strip * kTileCols); break;
+            case 2: prepare_tile<2>(d, srcimg, y0, y1, strip * kTileCols); break;
+            case 3: prepare_tile<3>(d, srcimg, y0, y1, strip * kTileCols); break;
+            default: prepare_tile<4>(d, srcimg, y0, y1, strip * kTileCols); break;
         }
     }
 }
 
-__global__ void prepare_single_kernel(Img d) {
+__global__ __launch_bounds__(256) void prepare_single_kernel(Img d) {
     if (blockIdx.x == 0 && threadIdx.x == 0) write_single_header(d);
-    prepare_rows(d, blockIdx.x, gridDim.x);
+    prepare_image(d, blockIdx.x, gridDim.x);
 }
 
-__global__ void prepare_batch_kernel(const Img* __restrict__ imgs, int n) {
+__global__ __launch_bounds__(256) void prepare_batch_kernel(const Img* __restrict__ imgs, int n) {
     const int i = blockIdx.y;
     if (i < n) {
-        Img d = imgs[i];
-        prepare_rows(d, blockIdx.x, gridDim.x);
+        const Img d = imgs[i];
+        prepare_image(d, blockIdx.x, gridDim.x);
     }
 }
 
@@ -1422,7 +1512,8 @@ hipError_t launch_energy_i32(const uint8_t* img, int H, int W, int C, long long 
 }
 
 hipError_t launch_prepare_single(const Img& d, hipStream_t st) {
-    const int blocks = d.H < 2048 ? d.H : 2048;
+    const int tiles = ((d.W + kTileCols - 1) / kTileCols) * ((d.H + kTileRows - 1) / kTileRows);
+    const int blocks = tiles < 4096 ? tiles : 4096;
     hipLaunchKernelGGL(prepare_single_kernel, dim3(blocks), dim3(256), 0, st, d);
     return hipGetLastError();
 }
@@ -1434,7 +1525,9 @@ hipError_t launch_prepare_from_i32(const Img& d, const int32_t* e, hipStream_t s
 }
 
 hipError_t launch_prepare_batch(const Img* imgs, int n, int max_rows, hipStream_t st) {
-    const int per = max_rows < 64 ? max_rows : 64;
+    // workgroups per image: enough for the tiles of a tall image (each takes every per-th tile)
+    const int chunks = (max_rows + kTileRows - 1) / kTileRows;
+    const int per = chunks < 64 ? chunks : 64;
     hipLaunchKernelGGL(prepare_batch_kernel, dim3(per, n), dim3(256), 0, st, imgs, n);
     return hipGetLastError();
 }
