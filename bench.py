@@ -526,7 +526,7 @@ def forward_byte_model(H: int, W: int, C: int, k: int) -> int:
 
 def forward(args, dev):
     """Forward-energy carve (sec. "Forward Energy Calculation") of the batched workload: the same
-    256 images as the default benchmark, one 1024-thread workgroup per image."""
+    256 images as the default benchmark, each carved by a team of 256-thread workgroups on one XCD."""
     import torch
 
     import synth
@@ -577,7 +577,7 @@ def forward(args, dev):
                                "H,W~U[240,2160], 10-40% of width removed (seed 3)",
                    "images": len(jobs), "pixel_seams": pixel_seams},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": fwd_traffic, "kernel": "fwd_carve_kernel",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": fwd_traffic, "kernel": "fwt_carve_kernel",
                      "model_bytes_per_launch": model_bytes, "kernel_ms": round(carve_ms, 3)},
         "copy_pass_ms": round(copy_ms, 3),
         "latency_ms": {"p50": round(pct(lat_ms, 50), 2), "p99": round(pct(lat_ms, 99), 2),
@@ -623,7 +623,14 @@ def forward_single(args, dev):
                       "data": "synthetic",
                       "config": {"workload": "forward-energy carve: one 1920x1080 RGB uint8 blob+noise image "
                                              "(seed 1) to 1440 columns", "pixel_seams": ps},
-                      "gpu_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 3)}), flush=True)
+                      "gpu_ms_per_step": round(e0.elapsed_time(e1) / args.steps, 3),
+                      "stages_ms_last_call": _stage_ms(api, ws, ["dp", "backtrack_removal"])}), flush=True)
+
+
+def _stage_ms(api, ws, names):
+    """Per-stage device clocks of the last carve in a single-image workspace, in ms."""
+    st = api.read_stages(ws, 1)[0]  # seconds
+    return {n: round(float(st[i]) * 1000.0, 3) for i, n in enumerate(names)}
 
 
 def object_byte_model(h: int, w0: int, C: int, seams: np.ndarray) -> int:

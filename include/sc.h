@@ -261,7 +261,9 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
  * outside the row is clamped to it (so a border pixel costs its difference to
  * the pixel that becomes the border).  Ties, backtrack, removal and the seam
  * loop are those of sc_carve; the costs are recomputed from the current pixels
- * for every seam.  One 1024-thread workgroup carves one image.
+ * for every seam.  A team of 256-thread workgroups on one XCD carves one
+ * image: each computes 976 columns (exact ones owned, 56 on each side shared
+ * with the neighbours at every 56-row phase end).
  *
  * sc_carve_forward: arguments as sc_carve (no tune); seams_out/costs_out
  *   (nullable) receive every seam and its forward cost.  ws: at least

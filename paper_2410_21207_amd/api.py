@@ -402,7 +402,7 @@ class BatchCarver:
 
 
 class ForwardBatch:
-    """Forward-energy carve of many images of uneven sizes, one workgroup per image.
+    """Forward-energy carve of many images of uneven sizes, each by a team of workgroups on one XCD.
 
     ``prepare()`` uploads the image descriptors (synchronous); ``launch()`` enqueues the copy-in
     pass and the carve with no host-to-device copy and no allocation.

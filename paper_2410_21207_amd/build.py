@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libseamcarve.so")
-SOURCES = [os.path.join(CSRC, n) for n in ("sc_kernels.hip", "sc_object.hip", "sc_api.cpp")]
+SOURCES = [os.path.join(CSRC, n) for n in ("sc_kernels.hip", "sc_object.hip", "sc_forward.hip", "sc_api.cpp")]
 HEADERS = [os.path.join(CSRC, "sc_internal.h"), os.path.join(CSRC, "sc_device.h"), os.path.join(ROOT, "include", "sc.h")]
 ARCH = os.environ.get("SC_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

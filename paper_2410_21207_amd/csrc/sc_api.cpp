@@ -661,28 +661,31 @@ extern "C" sc_status sc_slots_step_timed(const void* table, int n_slots, int max
 }
 
 // ---------------------------------------------------------------------------------------------
-// Forward energy (sec. "Forward Energy Calculation"): one workgroup per image, no energy plane.
+// Forward energy (sec. "Forward Energy Calculation"): teams of 256-thread workgroups on one XCD,
+// a dword per working pixel, no energy plane.
 namespace {
 
 struct FwdLayout {
-    size_t dirs, anc, seam, ro, wk, total;
-    int db, wp;
+    size_t dirs, anc, xq, amk, wk, total;
+    int db, wp, xw, P;
 };
 
 FwdLayout fwd_layout(int H, int W, int C) {
+    (void)C;
     FwdLayout L;
-    const int P = (H + sc::kFwdPhaseRows - 1) / sc::kFwdPhaseRows;
+    L.P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
     L.db = (int)sc::align_up((size_t)(W + 3) / 4, 16);  // direction bytes (4 columns each) per row
-    L.wp = (int)sc::align_up((size_t)W * C, 64);
+    L.wp = (int)sc::align_up((size_t)W * 4, 64);         // one dword per pixel
+    L.xw = (int)sc::align_up((size_t)W + 8, 64);
     size_t off = 0;
     L.dirs = off;
     off = sc::align_up(off + (size_t)((H + 3) / 4) * L.db * 4, sc::kAlign);  // rows grouped by four
-    L.anc = off;  // phase ancestors, used when they do not fit in LDS
-    off = sc::align_up(off + (size_t)P * W, sc::kAlign);
-    L.seam = off;
-    off = sc::align_up(off + (size_t)H * 4, sc::kAlign);
-    L.ro = off;
-    off = sc::align_up(off + (size_t)H * 4, sc::kAlign);
+    L.anc = off;
+    off = sc::align_up(off + (size_t)L.P * W, sc::kAlign);
+    L.xq = off;
+    off = sc::align_up(off + (size_t)2 * L.xw * 4, sc::kAlign);
+    L.amk = off;
+    off = sc::align_up(off + 2 * sizeof(unsigned long long), sc::kAlign);
     L.wk = off;
     off = sc::align_up(off + (size_t)H * L.wp + sc::kFwdSlack, sc::kAlign);
     L.total = off;
@@ -693,14 +696,22 @@ sc_status check_fwd_image(int H, int W, int C, int pitch) {
     sc_status s = check_image(H, W, C, pitch);
     if (s != SC_OK) return s;
     if (W > sc::kFwdMaxW) return fail(SC_EUNSUPPORTED, "W=%d > %d (forward energy)", W, sc::kFwdMaxW);
-    if ((long long)H * (long long)sc::align_up((size_t)W * C, 64) + (long long)sc::kFwdSlack >= (1ll << 31))
-        return fail(SC_EUNSUPPORTED, "image of %lld bytes too large for the forward-energy path",
-                    (long long)H * W * C);
+    if (H > sc::kFwdMaxH) return fail(SC_EUNSUPPORTED, "H=%d > %d (forward energy)", H, sc::kFwdMaxH);
+    if ((long long)H * (long long)sc::align_up((size_t)W * 4, 64) + (long long)sc::kFwdSlack >= (1ll << 31))
+        return fail(SC_EUNSUPPORTED, "image of %lld pixels too large for the forward-energy path", (long long)H * W);
     return SC_OK;
 }
 
+// DP members of a forward team (the members whose windows cover the columns) and the team size
+// that also gives every wave of the team at most one phase of rows to walk and remove.
+int fwd_dp_members(int W) { return W <= sc::kFwtSingle ? 1 : (W + sc::kFwtOwned - 1) / sc::kFwtOwned; }
+int fwd_team_target(int H, int W) {
+    const int P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
+    return std::min(32, std::max(fwd_dp_members(W), (P + 3) / 4));
+}
+
 sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
-                     int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl) {
+                     int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl, int G) {
     const FwdLayout L = fwd_layout(H, W, C);
     sc::Img d;
     memset(&d, 0, sizeof(d));
@@ -715,15 +726,17 @@ sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long
     d.costs_out = reinterpret_cast<long long*>(costs_out);
     d.dirs = reinterpret_cast<uint8_t*>(base + L.dirs);
     d.anc = reinterpret_cast<int8_t*>(base + L.anc);
-    d.seam = reinterpret_cast<int32_t*>(base + L.seam);
-    d.ro = reinterpret_cast<int32_t*>(base + L.ro);
+    d.xq = reinterpret_cast<uint32_t*>(base + L.xq);
+    d.xw = L.xw;
+    d.amk = reinterpret_cast<unsigned long long*>(base + L.amk);
     d.wk = reinterpret_cast<uint8_t*>(base + L.wk);
     d.wp = L.wp;
     d.db = L.db;
+    d.P = L.P;
     d.amin = &ctl->amin;
     d.bar = &ctl->bar;
     d.status = &ctl->status;
-    d.G = 1;
+    d.G = G;
     return d;
 }
 
@@ -736,7 +749,7 @@ double fwd_work(const sc_job& j) {  // pixel-seams: rows times the widths the se
 
 extern "C" size_t sc_forward_workspace_bytes(int H, int W, int C) {
     if (H < 1 || W < 1 || C < 1 || C > 4) return 0;
-    return ctl_region(1) + fwd_layout(H, W, C).total;
+    return ctl_region(1) + sc::align_up(sizeof(sc::Img), sc::kAlign) + fwd_layout(H, W, C).total;
 }
 
 extern "C" sc_status sc_carve_forward(uint8_t* img, int H, int W, int C, int target_w, int pitch, int32_t* seams_out,
@@ -750,12 +763,21 @@ extern "C" sc_status sc_carve_forward(uint8_t* img, int H, int W, int C, int tar
     if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     char* base = static_cast<char*>(ws);
     sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
-    const sc::Img d = make_fwd_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out, base + ctl_region(1), ctl);
+    const size_t off_img = ctl_region(1);
+    const int G = fwd_team_target(H, W);
+    const sc::Img d = make_fwd_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out,
+                                   base + off_img + sc::align_up(sizeof(sc::Img), sc::kAlign), ctl, G);
+    // header (magic, one image) and the descriptor, which the kernels read from the workspace
+    WsHead h;
+    memset(&h, 0, sizeof(h));
+    h.magic = kMagic;
+    h.n = 1;
     hipStream_t st = (hipStream_t)stream;
-    // the prepare pass also writes the descriptor into the workspace header, where the carve reads it
-    hipError_t e = sc::launch_prepare_single(d, st);
-    if (e == hipSuccess && target_w < W)
-        e = sc::launch_fwd_carve(reinterpret_cast<const sc::Img*>(base + sc::kWsImgOffset), nullptr, 1, W, st);
+    hipError_t e = hipMemcpyAsync(base, &h, sizeof(h), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + off_img, &d, sizeof(d), hipMemcpyHostToDevice, st);
+    const sc::Img* dd = reinterpret_cast<const sc::Img*>(base + off_img);
+    if (e == hipSuccess) e = sc::launch_fwt_prepare(dd, 1, H, st);
+    if (e == hipSuccess && target_w < W) e = sc::launch_fwt_carve(dd, nullptr, 8 * G, 0, st);
     if (e != hipSuccess) return hip_fail(e, "forward carve launch");
     return ok();
 }
@@ -764,7 +786,7 @@ extern "C" size_t sc_forward_batch_workspace_bytes(const sc_job* jobs, int n) {
     if (!jobs || n < 1) return 0;
     size_t total = ctl_region(n);
     total += sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
-    total += sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    total += sc::align_up((size_t)8 * 32 * n * sizeof(int2), sc::kAlign);
     for (int i = 0; i < n; ++i) {
         if (jobs[i].H < 1 || jobs[i].W < 1 || jobs[i].C < 1 || jobs[i].C > 4) return 0;
         total += fwd_layout(jobs[i].H, jobs[i].W, jobs[i].C).total;
@@ -776,7 +798,7 @@ extern "C" sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* w
                                               sc_batch_info* info) {
     if (!jobs || n < 1 || !ws || !info) return fail(SC_EINVAL, "null pointer or n < 1");
     if ((uintptr_t)ws % sc::kAlign) return fail(SC_EINVAL, "workspace must be %zu-byte aligned", sc::kAlign);
-    int max_w = 1, max_rows = 1;
+    int max_rows = 1;
     for (int i = 0; i < n; ++i) {
         const sc_job& j = jobs[i];
         sc_status s = check_fwd_image(j.H, j.W, j.C, j.pitch);
@@ -784,14 +806,56 @@ extern "C" sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* w
         if (!j.img) return fail(SC_EINVAL, "job %d: null image", i);
         if (j.target_w < 1 || j.target_w > j.W)
             return fail(SC_EINVAL, "job %d: target_w=%d not in [1, %d]", i, j.target_w, j.W);
-        max_w = std::max(max_w, j.W);
         max_rows = std::max(max_rows, j.H);
     }
     const size_t need = sc_forward_batch_workspace_bytes(jobs, n);
     if (ws_bytes < need) return fail(SC_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+
+    // Teams.  Every team's workgroups must be resident at once on one XCD (they wait for each
+    // other), so the whole plan fits the device's resident workgroups: every image first gets its
+    // DP members, then images in order of decreasing work grow toward a team in which every wave
+    // walks and removes at most one phase of rows.
+    int dev = 0, ncu = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he != hipSuccess) return hip_fail(he, "device query");
+    // two thirds of the occupancy the runtime reports: a plan that needed every last slot could
+    // leave a team partly resident behind others (measured: planning for 3 workgroups per compute
+    // unit made teams wait out their barriers)
+    const int per_xcd = std::max(1, 2 * sc::fwt_blocks_per_cu() * ncu / 3 / 8);
+    std::vector<int> order(n), gsz(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fwd_work(jobs[a]) > fwd_work(jobs[b]); });
+    long long used = 0;
+    for (int i = 0; i < n; ++i) used += gsz[i] = fwd_dp_members(jobs[i].W);
+    const long long cap = 8ll * per_xcd;
+    if (used > cap)
+        return fail(SC_EUNSUPPORTED, "%lld workgroups of forward teams exceed the %lld resident ones; split the batch",
+                    used, cap);
+    for (int i : order) {
+        const int grow = std::min<long long>(fwd_team_target(jobs[i].H, jobs[i].W) - gsz[i], cap - used);
+        if (grow > 0) gsz[i] += grow, used += grow;
+    }
+    // placement: longest first, each team on the XCD with the most free slots
+    int slots[8] = {0};
+    std::vector<int2> blk;
+    for (int i : order) {
+        int x = 0;
+        for (int c = 1; c < 8; ++c)
+            if (slots[c] < slots[x]) x = c;
+        while (slots[x] + gsz[i] > per_xcd && gsz[i] > fwd_dp_members(jobs[i].W)) --gsz[i];
+        if (slots[x] + gsz[i] > per_xcd) return fail(SC_EUNSUPPORTED, "no XCD has room for the team of job %d", i);
+        for (int r = 0; r < gsz[i]; ++r) {
+            const size_t b = (size_t)x + 8 * (size_t)(slots[x] + r);
+            if (blk.size() <= b) blk.resize(b + 1, make_int2(-1, -1));
+            blk[b] = make_int2(i, r);
+        }
+        slots[x] += gsz[i];
+    }
+    if (blk.size() > (size_t)8 * 32 * n) return fail(SC_EUNSUPPORTED, "plan too large");
     const size_t off_imgs = ctl_region(n);
-    const size_t off_order = off_imgs + sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
-    size_t off_data = off_order + sc::align_up((size_t)n * sizeof(int), sc::kAlign);
+    const size_t off_blk = off_imgs + sc::align_up((size_t)n * sizeof(sc::Img), sc::kAlign);
+    size_t off_data = off_blk + sc::align_up((size_t)8 * 32 * n * sizeof(int2), sc::kAlign);
     std::vector<char> host(off_data, 0);
     WsHead* h = reinterpret_cast<WsHead*>(host.data());
     h->magic = kMagic;
@@ -802,38 +866,36 @@ extern "C" sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* w
         const sc_job& j = jobs[i];
         sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead)) + i;
         imgs[i] = make_fwd_img(j.src, j.img, j.H, j.W, j.C, j.pitch, j.target_w, j.seams_out, j.costs_out,
-                               base + off_data, ctl);
+                               base + off_data, ctl, gsz[i]);
         off_data += fwd_layout(j.H, j.W, j.C).total;
     }
-    // workgroups start in order of decreasing work, so the longest carves never wait for a slot
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fwd_work(jobs[a]) > fwd_work(jobs[b]); });
-    memcpy(host.data() + off_order, order.data(), n * sizeof(int));
+    memcpy(host.data() + off_blk, blk.data(), blk.size() * sizeof(int2));
     hipError_t e = hipMemcpy(ws, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "forward batch upload");
+    int teams = 0;
+    for (int i = 0; i < n; ++i) teams += gsz[i] > 1;
     memset(info, 0, sizeof(*info));
     info->n = n;
-    info->nblocks = n;
-    info->variant = max_w;  // widest image: selects the columns per thread
+    info->nblocks = (int)blk.size();
+    info->variant = -1;     // the forward kernel has one shape
     info->max_rows = max_rows;
     info->team = 0;         // marks a forward-energy batch
+    info->teams_used = teams;
     info->off_imgs = off_imgs;
-    info->off_blk = off_order;
+    info->off_blk = off_blk;
     return ok();
 }
 
 static sc_status fwd_batch_pass(const sc_batch_info* info, void* ws, void* stream, bool copy, bool carve) {
-    if (!info || !ws || info->n < 1 || info->nblocks != info->n || info->team != 0 || info->variant < 1 ||
-        info->variant > sc::kFwdMaxW)
+    if (!info || !ws || info->n < 1 || info->nblocks < 1 || info->team != 0 || info->variant != -1)
         return fail(SC_EINVAL, "not a forward-energy batch");
     char* base = static_cast<char*>(ws);
     const sc::Img* imgs = reinterpret_cast<const sc::Img*>(base + info->off_imgs);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    if (copy) e = sc::launch_prepare_batch(imgs, info->n, info->max_rows, st);
+    if (copy) e = sc::launch_fwt_prepare(imgs, info->n, info->max_rows, st);
     if (e == hipSuccess && carve)
-        e = sc::launch_fwd_carve(imgs, reinterpret_cast<const int*>(base + info->off_blk), info->n, info->variant, st);
+        e = sc::launch_fwt_carve(imgs, reinterpret_cast<const int2*>(base + info->off_blk), info->nblocks, 0, st);
     if (e != hipSuccess) return hip_fail(e, "forward batch launch");
     return ok();
 }

@@ -269,4 +269,91 @@ struct PixRow {
 
 };
 
+// ----------------------------------------------------------------------------------------------
+// Team barrier.  One workgroup: a workgroup barrier.  A team of G workgroups on one XCD: each
+// thread waits for its own stores to reach the L2 (vmcnt), then one thread per workgroup bumps
+// the image's counter with a device-scope atomic and polls it with device-scope loads until all
+// G have arrived; readers then fetch shared data with sc1 loads (see ld<true>).  The wait is
+// bounded: after ~10 s it flags the image and every member gives up on it.
+template <bool TEAM>
+__device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, int* flag) {
+    if constexpr (!TEAM) {
+        __syncthreads();
+        return true;
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            epoch += (unsigned)G;
+            __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long t0 = wall_clock64();
+            int ab = 0;
+            while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                __builtin_amdgcn_s_sleep(1);
+                if (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                    (kStatusTimeout | kStatusPlacement)) {
+                    ab = 1;
+                    break;
+                }
+                if (wall_clock64() - t0 > 1000000000ull) {  // 10 s at the 100 MHz constant clock
+                    __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                    break;
+                }
+            }
+            *flag = ab;
+        }
+        __syncthreads();
+        return *flag == 0;
+    }
+}
+
+// Reset the control words of one image (every carve launch starts from them).
+__device__ __forceinline__ void reset_ctl(const Img& d) {
+    Ctl* c = reinterpret_cast<Ctl*>(d.amin);
+    c->amin = ~0ull;
+    c->bar = 0;
+    c->status = 0;
+    c->t_begin = c->t_end = 0;
+    c->xmask = 0;
+    c->done = 0;
+    c->t_stage[0] = c->t_stage[1] = c->t_stage[2] = 0;
+}
+
+// One source row as seen by a thread owning 4 pixels from column x0: the aligned dwords covering
+// the pixels and one neighbour on each side, realigned to the row's start with v_alignbyte (a
+// caller's rows may start at any byte).
+template <int C>
+struct SrcRow {
+    static constexpr int ND = C + 3;   // dwords loaded per thread
+    static constexpr uint32_t PMASK = C == 4 ? 0xFFFFFFFFu : (1u << (8 * C)) - 1u;
+    uint32_t r[C + 2];                 // row bytes [x0*C - 4, x0*C + 4*C + 4), dword aligned to the row
+
+    // Row y of the image (pitch bytes per row, W*C bytes used): the thread's pixels start at x0.
+    __device__ __forceinline__ void load(const uint8_t* img, long long pitch, int W, int y, int x0) {
+        const uint8_t* row = img + (long long)y * pitch;
+        const uint32_t sh = (uint32_t)((uintptr_t)row & 3u);
+        // the descriptor covers the whole dwords holding the row's bytes (a dword-aligned dword that
+        // holds an image byte lies inside the image's allocation); dwords outside are dropped (read
+        // as 0), and only clamped neighbours would use them
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(row - sh, (sh + (uint32_t)(W * C) + 3u) & ~3u);
+        // per-lane offsets never wrap: the dword left of column x0 has an offset of its own (dropped
+        // at x0 = 0), the others count up from column x0 (an immediate offset may be folded in)
+        const uint32_t v0 = x0 < W ? (uint32_t)(x0 * C) : kBufDrop;
+        const uint32_t vl = x0 < W && x0 > 0 ? (uint32_t)(x0 * C - 4) : kBufDrop;
+        uint32_t d[ND];
+        d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vl, 0, 0);
+#pragma unroll
+        for (int m = 1; m < ND; ++m) d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(v0 + 4u * (m - 1)), 0, 0);
+#pragma unroll
+        for (int m = 0; m < C + 2; ++m) r[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
+    }
+    // pixel p of the thread (p = -1 .. 4), channels packed in the low bytes
+    __device__ __forceinline__ uint32_t px(int p) const {
+        const int o = 4 + p * C, q = o >> 2, b = o & 3;
+        const uint32_t v = b == 0 ? r[q] : __builtin_amdgcn_alignbyte(r[q + 1], r[q], (uint32_t)b);
+        return v & PMASK;
+    }
+};
+
 }  // namespace sc

@@ -31,6 +31,7 @@ struct Img {
     int G;                     // team size (workgroups) carving this image
     int mode;                  // 0 = carve, 1 = one seam only, no removal (sc_dp_seam)
     int minside;               // 1 = remove a seam pixel by moving the shorter side of its row
+    unsigned long long* amk;   // forward teams: the argmin words of even and odd seams
 };
 
 // Control words of one image (zeroed by the energy pass of every launch).
@@ -103,13 +104,27 @@ hipError_t launch_insert_seams(const uint8_t* img, int H, int W, int C, long lon
                                uint8_t* out, long long out_pitch, hipStream_t st);
 constexpr int kInsertMaxWidth = 65536;
 
-// Forward-energy carve (one 1024-thread workgroup per image).  Widths up to 4096 use 4 columns per
-// thread, up to kFwdMaxW 8.  Loads of a row may read up to kFwdSlack bytes past the last row of wk.
+// Limits of the one-workgroup-row kernels (object removal) and the forward teams: widths up to
+// kFwdMaxW, rows up to kFwdMaxH; loads of a row may read up to kFwdSlack bytes past the last row of
+// a working copy.  kFwdPhaseRows: rows per backtrack phase of the object-removal DP.
 constexpr int kFwdMaxW = 8192;
 constexpr int kFwdMaxH = 16448;
-constexpr int kFwdPhaseRows = 60;  // rows per backtrack phase of the forward DP
+constexpr int kFwdPhaseRows = 60;
 constexpr size_t kFwdSlack = 256;
-hipError_t launch_fwd_carve(const Img* imgs, const int* order, int n, int max_w, hipStream_t st);
+
+// Forward-energy carve by teams of 256-thread workgroups on one XCD (sc_forward.hip).  A working
+// pixel is one dword.  Member g of a team with more than one DP member computes columns
+// [g*kFwtOwned - kFwtPhaseRows, (g+1)*kFwtOwned + kFwtPhaseRows) and owns [g*kFwtOwned,
+// (g+1)*kFwtOwned); a team of images up to kFwtSingle columns has one DP member.  blk: block ->
+// (image, member), or nullptr for one image whose members are blocks xcd, xcd + 8, ...
+constexpr int kFwtThreads = 256;
+constexpr int kFwtWindow = 976;  // 4 waves x 240 exact columns + 8 ghost columns on each side
+constexpr int kFwtPhaseRows = 56;
+constexpr int kFwtOwned = kFwtWindow - 2 * kFwtPhaseRows;
+constexpr int kFwtSingle = kFwtWindow - 8;  // widest image a single DP member carves
+hipError_t launch_fwt_prepare(const Img* imgs, int n, int max_rows, hipStream_t st);
+hipError_t launch_fwt_carve(const Img* imgs, const int2* blk, int nblocks, int xcd, hipStream_t st);
+int fwt_blocks_per_cu();
 
 // Object removal with a mask (one 1024-thread workgroup per image, the forward kernel's limits:
 // frame width <= kFwdMaxW, frame rows <= kFwdMaxH).  The carved frame is h = H rows by W columns

@@ -89,16 +89,6 @@ __global__ void energy_i32_kernel(const uint8_t* __restrict__ img, int H, int W,
         *gp(out + (long long)y * W + x) = (int32_t)energy_at(img, pitch, H, W, C, y, x);
 }
 
-__device__ __forceinline__ void reset_ctl(const Img& d) {
-    Ctl* c = reinterpret_cast<Ctl*>(d.amin);
-    c->amin = ~0ull;
-    c->bar = 0;
-    c->status = 0;
-    c->t_begin = c->t_end = 0;
-    c->xmask = 0;
-    c->done = 0;
-    c->t_stage[0] = c->t_stage[1] = c->t_stage[2] = 0;
-}
 
 // A single-image workspace starts with a header: magic, image count, then the descriptor itself
 // (read by the step-wise carve kernel), then the image's Ctl block.
@@ -127,39 +117,6 @@ __device__ __forceinline__ void clear_exchange(const Img& d) {
 // of wk.
 constexpr int kTileRows = 32;
 constexpr int kTileCols = 1024;  // 256 threads x 4 pixels
-
-template <int C>
-struct SrcRow {
-    static constexpr int ND = C + 3;   // dwords loaded per thread
-    static constexpr uint32_t PMASK = C == 4 ? 0xFFFFFFFFu : (1u << (8 * C)) - 1u;
-    uint32_t r[C + 2];                 // row bytes [x0*C - 4, x0*C + 4*C + 4), dword aligned to the row
-
-    // Row y of the image (pitch bytes per row, W*C bytes used): the thread's pixels start at x0.
-    __device__ __forceinline__ void load(const uint8_t* img, long long pitch, int W, int y, int x0) {
-        const uint8_t* row = img + (long long)y * pitch;
-        const uint32_t sh = (uint32_t)((uintptr_t)row & 3u);
-        // the descriptor covers the whole dwords holding the row's bytes (a dword-aligned dword that
-        // holds an image byte lies inside the image's allocation); dwords outside are dropped (read
-        // as 0), and only clamped neighbours would use them
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(row - sh, (sh + (uint32_t)(W * C) + 3u) & ~3u);
-        // per-lane offsets never wrap: the dword left of column x0 has an offset of its own (dropped
-        // at x0 = 0), the others count up from column x0 (an immediate offset may be folded in)
-        const uint32_t v0 = x0 < W ? (uint32_t)(x0 * C) : kBufDrop;
-        const uint32_t vl = x0 < W && x0 > 0 ? (uint32_t)(x0 * C - 4) : kBufDrop;
-        uint32_t d[ND];
-        d[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)vl, 0, 0);
-#pragma unroll
-        for (int m = 1; m < ND; ++m) d[m] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(v0 + 4u * (m - 1)), 0, 0);
-#pragma unroll
-        for (int m = 0; m < C + 2; ++m) r[m] = __builtin_amdgcn_alignbyte(d[m + 1], d[m], sh);
-    }
-    // pixel p of the thread (p = -1 .. 4), channels packed in the low bytes
-    __device__ __forceinline__ uint32_t px(int p) const {
-        const int o = 4 + p * C, q = o >> 2, b = o & 3;
-        const uint32_t v = b == 0 ? r[q] : __builtin_amdgcn_alignbyte(r[q + 1], r[q], (uint32_t)b);
-        return v & PMASK;
-    }
-};
 
 template <int C>
 __device__ void prepare_tile(const Img& d, const uint8_t* srcimg, int y0, int y1, int xs) {
@@ -386,45 +343,6 @@ __global__ void transpose_kernel(const uint8_t* __restrict__ src, int H, int W, 
         const int x = bx + r, y = by + tx;  // output row x, column y
         if (y < H && x < W)
             for (int c = 0; c < C; ++c) *gp(dst + (long long)x * dp + (long long)y * C + c) = tile[tx][r * C + c];
-    }
-}
-
-// ----------------------------------------------------------------------------------------------
-// Team barrier.  One workgroup: a workgroup barrier.  A team of G workgroups on one XCD: each
-// thread waits for its own stores to reach the L2 (vmcnt), then one thread per workgroup bumps
-// the image's counter with a device-scope atomic and polls it with device-scope loads until all
-// G have arrived; readers then fetch shared data with sc1 loads (see ld<true>).  The wait is
-// bounded: after ~10 s it flags the image and every member gives up on it.
-template <bool TEAM>
-__device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, int* flag) {
-    if constexpr (!TEAM) {
-        __syncthreads();
-        return true;
-    } else {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            epoch += (unsigned)G;
-            __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned long long t0 = wall_clock64();
-            int ab = 0;
-            while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
-                __builtin_amdgcn_s_sleep(1);
-                if (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-                    (kStatusTimeout | kStatusPlacement)) {
-                    ab = 1;
-                    break;
-                }
-                if (wall_clock64() - t0 > 1000000000ull) {  // 10 s at the 100 MHz constant clock
-                    __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ab = 1;
-                    break;
-                }
-            }
-            *flag = ab;
-        }
-        __syncthreads();
-        return *flag == 0;
     }
 }
 
@@ -1124,310 +1042,6 @@ __global__ __launch_bounds__(kInsertThreads) void insert_seams_kernel(const uint
     }
 }
 
-// ----------------------------------------------------------------------------------------------
-// Forward energy (sec. "Forward Energy Calculation", the standard definition with no per-pixel
-// term): the DP cost of removing pixel (i,j) is the difference of the pixel pairs its removal
-// makes neighbours, CU = D(left, right), plus D(up, left) when the seam comes from the upper-left
-// parent or D(up, right) from the upper-right one.  D sums |difference| over the channels (one
-// v_sad_u8 on packed pixels) and a neighbour index outside the row is clamped to it.  The costs
-// come from the current pixels, so there is no energy plane and no band update: every row of the
-// DP reads two rows of the working copy.
-//
-// One workgroup of 1024 threads carves one image; thread t owns columns [CPL*t, CPL*t + CPL).
-// Between rows a column's state is one word M << 9 | a, a = 64 + (ancestor column in the last
-// row before the current K-row phase) - (column).  A row forms three candidate words per column
-// (upper-left, up, upper-right: tags 0, 1, 2 in bits 7-8, pair costs added to M) and one
-// v_min3_u32 picks the cheapest with ties to the leftmost parent, carrying the parent's ancestor
-// offset along.  M <= 255*C*H < 2^23 under the library's limit H*510*C <= 8388000.  Neighbour
-// states cross threads through LDS with one barrier per row (LDS-only fences: the pixel rows
-// loaded PF rows ahead stay in flight).  At the end of each phase the ancestor offsets go to LDS
-// (to the workspace when they do not fit), so the backtrack hops phase by phase and then walks
-// the K rows of every phase in parallel from an LDS window of the 2-bit direction map.  Removal
-// moves the pixels right of the seam one column left with the in-place slot shifter.
-
-namespace fwd {
-constexpr int NT = 1024;
-constexpr int NW = NT / 64;
-constexpr int K = kFwdPhaseRows;            // rows per phase: the ancestor offset stays in [4, 124]
-constexpr int GK = K / 4;                   // 4-row direction groups per phase
-constexpr int WD = 32;                      // window dwords per group: columns je-59 .. je+59
-constexpr int PF = 8;                       // rows of pixels loaded ahead
-constexpr int PMAX = (kFwdMaxH + K - 1) / K;
-constexpr int ANC_LDS = 96 * 1024;          // phase ancestors kept in LDS up to this many bytes
-constexpr uint32_t INF = 0xFFFFFFFFu;
-static_assert(K % 4 == 0 && K <= 63 && PF % 4 == 0, "phase shape");
-
-struct Smem {
-    uint32_t xa[2][NT + 1];  // first column state of thread t at [t]
-    uint32_t xb[2][NT + 1];  // last column state of thread t at [t + 1]
-    uint32_t win[NW][GK * WD];
-    int jend[PMAX];          // seam column at the last row of every phase
-    unsigned long long red[NW];
-    uint8_t anc[ANC_LDS];
-};
-
-template <int C, int CPL>
-struct Carver : PixRow<C, CPL> {
-    using Row = PixRow<C, CPL>;
-    using Row::load_row;
-    using Row::pixels;
-    static constexpr int NDW = Row::NDW;
-
-    static __device__ __forceinline__ void carve(const Img& d, Smem& sm) {
-        const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-        const int H = d.H, j0 = t * CPL;
-        const int nseams = d.W - d.target_w;
-        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
-        if (t == 0) ctl->t_begin = wall_clock64();
-        const __amdgpu_buffer_rsrc_t rwk = make_rsrc(d.wk, (uint32_t)H * (uint32_t)d.wp + (uint32_t)kFwdSlack);
-        const uint32_t gbytes = (uint32_t)d.db * 4u;  // bytes of one 4-row group of the direction map
-        const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * gbytes);
-        const int P = (H + K - 1) / K;
-        int w = d.W;
-#pragma unroll 1
-        for (int k = 0; k < nseams; ++k, --w) {
-            const unsigned long long tm0 = t == 0 ? wall_clock64() : 0ull;
-            const bool act = j0 < w;
-            // per-lane byte offsets of column j0 and of the dword left of it in a row; dropped for
-            // idle threads and left of column 0 (that neighbour is clamped to column 0 below)
-            const uint32_t v0 = act ? (uint32_t)(j0 * C) : kBufDrop;
-            const uint32_t vl = act && j0 > 0 ? (uint32_t)(j0 * C - 4) : kBufDrop;
-            // phase ancestors: LDS, or the workspace when they do not fit.  Two explicit paths, not
-            // one generic pointer: a flat store would make every later LDS wait also wait for the
-            // pixel loads in flight.
-            const bool anc_lds = P * w <= ANC_LDS;
-            uint8_t* const ancg = reinterpret_cast<uint8_t*>(d.anc);
-            bool okR[CPL];  // column j0+c has a right neighbour
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) okR[c] = j0 + c + 1 < w;
-
-            // ---- DP over the rows (a3 with forward costs)
-            // The row loop keeps its per-row overhead small: a wave with no column in range only
-            // joins the H-1 row barriers, the others run with no per-lane branches (idle lanes of
-            // the boundary wave compute values nobody reads; their loads and stores are dropped),
-            // row 0 and the last row are tested only where they can occur, and phases end on a
-            // scalar countdown.
-            // Rows go in blocks of PF with the ring slot of a row refilled right after its pixels
-            // are taken.  The refills of full blocks are unconditional (clamped to the last row),
-            // so no ring register is merged across a branch: a merge would need a copy of a
-            // register whose load is still in flight, i.e. a wait for every outstanding load.
-            uint32_t S[CPL];
-            if (wv * 64 * CPL >= w) {
-#pragma unroll 1
-                for (int i = 1; i < H; ++i) lds_barrier();
-            } else {
-                uint32_t ring[PF][NDW];
-                static_for<PF>([&](auto U) {
-                    constexpr int u = decltype(U)::value;
-                    load_row(ring[u], rwk, vl, v0, (uint32_t)min(u, H - 1) * (uint32_t)d.wp);
-                });
-                uint32_t Pup[CPL], dacc[CPL / 4];
-#pragma unroll
-                for (int q = 0; q < CPL / 4; ++q) dacc[q] = 0;
-                int kleft = K, phase = 0;  // rows left in the current phase; its index
-                auto row = [&](auto U, int i, auto LAST) {
-                    constexpr int u = decltype(U)::value;
-                    constexpr bool last = decltype(LAST)::value;  // the block holds row H-1: no refill
-                    uint32_t Pc[CPL + 2];
-                    pixels(ring[u], Pc);
-                    if (!last) load_row(ring[u], rwk, vl, v0, (uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp);
-                    if (t == 0) Pc[0] = Pc[1];  // left neighbour of column 0 clamped to it
-                    uint32_t bits = 0;
-                    if (u == 0 && i == 0) {
-#pragma unroll
-                        for (int c = 0; c < CPL; ++c) {
-                            const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
-                            S[c] = (__builtin_amdgcn_sad_u8(Pc[c], pr, 0u) << 9) | 64u;
-                            bits |= 1u << (2 * c);
-                        }
-                    } else {
-                        const int b = i & 1;
-                        sm.xa[b][t] = S[0];
-                        sm.xb[b][t + 1] = S[CPL - 1];
-                        lds_barrier();
-                        const uint32_t Sl = sm.xb[b][t], Sr = sm.xa[b][t + 1];
-                        uint32_t Sn[CPL];
-#pragma unroll
-                        for (int c = 0; c < CPL; ++c) {
-                            const uint32_t pl = Pc[c];
-                            const uint32_t pr = okR[c] ? Pc[c + 2] : Pc[c + 1];
-                            const uint32_t cu = __builtin_amdgcn_sad_u8(pl, pr, 0u);
-                            const uint32_t sL = c == 0 ? Sl : S[c - 1];
-                            const uint32_t sR = c == CPL - 1 ? Sr : S[c + 1];
-                            uint32_t kL = (__builtin_amdgcn_sad_u8(Pup[c], pl, 0u) << 9) + sL;
-                            if (c == 0 && t == 0) kL = INF;  // column 0 has no upper-left parent
-                            const uint32_t kU = S[c] | 0x80u;
-                            const uint32_t kR =
-                                okR[c] ? ((__builtin_amdgcn_sad_u8(Pup[c], pr, 0u) << 9) + sR) | 0x100u : INF;
-                            const uint32_t kk = min3u(kL, kU, kR);
-                            Sn[c] = next_state(kk, cu);
-                            bits |= ((kk >> 7) & 3u) << (2 * c);
-                        }
-#pragma unroll
-                        for (int c = 0; c < CPL; ++c) S[c] = Sn[c];
-                    }
-#pragma unroll
-                    for (int c = 0; c < CPL; ++c) Pup[c] = Pc[c + 1];
-#pragma unroll
-                    for (int q = 0; q < CPL / 4; ++q) dacc[q] |= ((bits >> (8 * q)) & 0xFFu) << (8 * (u & 3));
-                    if ((u & 3) == 3 || (last && i == H - 1)) {
-#pragma unroll
-                        for (int q = 0; q < CPL / 4; ++q) {
-                            const uint32_t vo = j0 + 4 * q < w ? (uint32_t)(j0 / 4 + q) * 4u : kBufDrop;
-                            __builtin_amdgcn_raw_buffer_store_b32(dacc[q], rdir, (int)vo, (int)((uint32_t)(i >> 2) * gbytes), 0);
-                            dacc[q] = 0;
-                        }
-                    }
-                    if (--kleft == 0 || (last && i == H - 1)) {
-                        // end of a phase: record the ancestor offsets, then restart them
-#pragma unroll
-                        for (int c = 0; c < CPL; ++c) {
-                            if (j0 + c < w) {
-                                if (anc_lds) sm.anc[phase * w + j0 + c] = (uint8_t)(S[c] & 0x7Fu);
-                                else *gp(ancg + phase * w + j0 + c) = (uint8_t)(S[c] & 0x7Fu);
-                            }
-                            S[c] = (S[c] & ~0x7Fu) | 64u;
-                        }
-                        kleft = K;
-                        ++phase;
-                    }
-                };
-                int i0 = 0;
-#pragma unroll 1
-                for (; i0 + PF < H; i0 += PF)
-                    static_for<PF>([&](auto U) { row(U, i0 + decltype(U)::value, std::false_type{}); });
-                static_for<PF>([&](auto U) {
-                    if (i0 + decltype(U)::value < H) row(U, i0 + decltype(U)::value, std::true_type{});
-                });
-            }
-
-            // ---- argmin of the last row (a4): packed (M << 32 | column), the leftmost minimum
-            unsigned long long best = ~0ull;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c)
-                if (j0 + c < w) best = min(best, ((unsigned long long)(S[c] >> 9) << 32) | (unsigned)(j0 + c));
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) best = min(best, (unsigned long long)__shfl_xor((long long)best, o));
-            if (lane == 0) sm.red[wv] = best;
-            __syncthreads();
-            const unsigned long long tm1 = t == 0 ? wall_clock64() : 0ull;
-            if (t == 0) {
-                unsigned long long b = sm.red[0];
-                for (int x = 1; x < NW; ++x) b = min(b, sm.red[x]);
-                int je = (int)(b & 0xFFFFFFFFull);
-                if (d.costs_out) d.costs_out[k] = (long long)(b >> 32);
-                // ---- backtrack (a5), first hop: phase by phase through the ancestor offsets
-                sm.jend[P - 1] = je;
-                for (int p = P - 1; p > 0; --p) {
-                    const int a = anc_lds ? (int)sm.anc[p * w + je] : (int)*gp(ancg + p * w + je);
-                    je = min(max(je + a - 64, 0), w - 1);
-                    sm.jend[p - 1] = je;
-                }
-            }
-            __syncthreads();
-            // ---- then every phase's rows, one wave per phase, from an LDS window of the map
-#pragma unroll 1
-            for (int p = wv; p < P; p += NW) {
-                const int r0 = p * K, n = min(K, H - r0), ng = (n + 3) >> 2;
-                const int je = sm.jend[p];
-                const int cb0 = max(0, je - (K - 1)) >> 2;
-                uint32_t* win = sm.win[wv];
-                constexpr int NI = (GK * WD + 63) / 64;
-                uint32_t v[NI];
-                const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs) + (size_t)(r0 >> 2) * d.db;
-#pragma unroll
-                for (int m = 0; m < NI; ++m) {
-                    const int x = lane + 64 * m, g = x / WD, q = x % WD;
-                    v[m] = g < ng && cb0 + q < d.db ? *gp(src + (size_t)g * d.db + cb0 + q) : 0u;
-                }
-#pragma unroll
-                for (int m = 0; m < NI; ++m) {
-                    const int x = lane + 64 * m;
-                    if (x < GK * WD) win[x] = v[m];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                int s = je, mys = 0;
-                for (int i = n - 1; i >= 0; --i) {
-                    if (lane == i) mys = s;
-                    if (i > 0) {
-                        const int q = min(max((s >> 2) - cb0, 0), WD - 1);
-                        const uint32_t wd = win[(i >> 2) * WD + q];
-                        s += (int)((wd >> ((i & 3) * 8 + (s & 3) * 2)) & 3u) - 1;
-                        s = min(max(s, 0), w - 1);
-                    }
-                }
-                if (lane < n) {
-                    *gp(d.seam + r0 + lane) = mys;
-                    if (d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            __syncthreads();
-            const unsigned long long tm2 = t == 0 ? wall_clock64() : 0ull;
-            // ---- removal (a6): the pixels right of the seam move one column left, four rows per
-            // memory round trip (the shifter's four segments are four rows here); the 4-row groups
-            // are dealt to the waves round-robin so every wave moves about the same number of rows
-#pragma unroll 1
-            for (int r0 = wv * 4; r0 < H; r0 += NW * 4) {
-                const int n = min(4, H - r0);
-                const int sv = lane < n ? *gp(d.seam + r0 + lane) : 0;
-                auto seg = [&](int i) {
-                    if (i >= n) {
-                        SSeg g;
-                        g.base = d.wk;
-                        g.q0 = g.q1 = g.sh = g.n = 0;
-                        return g;
-                    }
-                    const int si = min(max(__builtin_amdgcn_readlane(sv, i), 0), w - 1);
-                    uint8_t* r = d.wk + (long long)(r0 + i) * d.wp;
-                    return sseg<false>(r + (long long)si * C, r + (long long)(w - 1) * C, C);
-                };
-                shift_rows2_wave<2, false, false>(seg(0), seg(1), seg(2), seg(3), lane);
-            }
-            __syncthreads();
-            if (t == 0) {  // device clock per stage: DP sweep; argmin + backtrack; removal
-                const unsigned long long tm3 = wall_clock64();
-                ctl->t_stage[0] += tm1 - tm0;
-                ctl->t_stage[1] += tm2 - tm1;
-                ctl->t_stage[2] += tm3 - tm2;
-            }
-        }
-        // ---- the carved rows go from wk to img
-        if (nseams > 0) {
-            const int nb = d.target_w * C;
-#pragma unroll 1
-            for (int r = wv; r < H; r += NW)
-                copy_bytes_wave(d.img + (long long)r * d.pitch, d.wk + (long long)r * d.wp, nb, lane);
-        }
-        __syncthreads();
-        if (t == 0) {
-            ctl->done = (unsigned)nseams;
-            ctl->t_end = wall_clock64();
-        }
-    }
-};
-}  // namespace fwd
-
-// One workgroup per image of `imgs`, in the order given by `order` (nullable: identity).
-template <int CPL>
-__global__ __launch_bounds__(fwd::NT, 1) void fwd_carve_kernel(const Img* __restrict__ imgs, const int* __restrict__ order,
-                                                               int n) {
-    __shared__ fwd::Smem sm;
-    if ((int)blockIdx.x >= n) return;
-    const Img d = imgs[order ? order[blockIdx.x] : blockIdx.x];
-    switch (d.C) {
-        case 1: fwd::Carver<1, CPL>::carve(d, sm); break;
-        case 2: fwd::Carver<2, CPL>::carve(d, sm); break;
-        case 3: fwd::Carver<3, CPL>::carve(d, sm); break;
-        default: fwd::Carver<4, CPL>::carve(d, sm); break;
-    }
-}
-
-// ----------------------------------------------------------------------------------------------
 // Launchers of the carve kernel variants (the table of shapes: SC_VARIANTS in sc_internal.h).
 hipError_t launch_carve_single(const Img& d, int v, int G, int xcd, hipStream_t st) {
     switch (v) {
@@ -1467,11 +1081,6 @@ hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, uns
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_carve(const Img* imgs, const int* order, int n, int max_w, hipStream_t st) {
-    if (max_w <= 4096) hipLaunchKernelGGL(fwd_carve_kernel<4>, dim3(n), dim3(fwd::NT), 0, st, imgs, order, n);
-    else hipLaunchKernelGGL(fwd_carve_kernel<8>, dim3(n), dim3(fwd::NT), 0, st, imgs, order, n);
-    return hipGetLastError();
-}
 
 hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st) {
     hipLaunchKernelGGL(slot_write_kernel, dim3(1), dim3(1), 0, st, table, slot, d);

@@ -28,11 +28,13 @@ hipError_t launch_insert_seams(const uint8_t*, int, int, int, long long, int, co
                                hipStream_t) {
     return kNo;
 }
-hipError_t launch_fwd_carve(const Img*, const int*, int, int, hipStream_t) { return kNo; }
 hipError_t launch_obj_reset(ObjCtl*, int, hipStream_t) { return kNo; }
 hipError_t launch_obj_carve(const ObjImg*, int, int, hipStream_t) { return kNo; }
 hipError_t launch_mask_bbox(const uint8_t*, int, int, long long, int*, hipStream_t) { return kNo; }
 hipError_t launch_copy_rows(const uint8_t*, long long, uint8_t*, long long, int, int, hipStream_t) { return kNo; }
+hipError_t launch_fwt_prepare(const Img*, int, int, hipStream_t) { return kNo; }
+hipError_t launch_fwt_carve(const Img*, const int2*, int, int, hipStream_t) { return kNo; }
+int fwt_blocks_per_cu() { return 3; }
 hipError_t noalloc_scratch(void**) { return kNo; }
 hipError_t launch_copy_status(const unsigned*, uint32_t*, hipStream_t) { return kNo; }
 }  // namespace sc

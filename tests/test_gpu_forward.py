@@ -1,9 +1,10 @@
 """GPU parity of the forward-energy carve against the oracle, bit for bit.
 
-Sizes span several 4-column thread tiles, ragged row tails of the 60-row backtrack phases,
-the 8-column path for widths above 4096, phase ancestors spilled from LDS to the workspace,
-every channel count, padded pitches, tie-heavy pixels and the degenerate shapes; the full
-batched workload is checked on sampled seams.
+Sizes span several 4-column lane groups and 240-column wave cores, ragged row tails of the
+56-row phases, images wider than one workgroup's 968 exact columns (teams of 2 to 9 DP members
+exchanging keys at phase ends), tall images with many phases, every channel count, padded
+pitches, tie-heavy pixels and the degenerate shapes; the full batched workload is checked on
+sampled seams.
 """
 import numpy as np
 import pytest
@@ -53,14 +54,14 @@ def test_forward_in_place():
 
 
 def test_forward_wide_path():
-    """W > 4096: eight columns per thread."""
+    """W > 4096: teams of five to nine DP members."""
     log("forward wide")
     _check(synth.blob_image(70, 4500, 3, seed=5), 4494)
     _check(rng_img(2, 9, 8192, 1, 3), 8189)
 
 
 def test_forward_ancestors_in_workspace():
-    """Phases x width beyond the LDS budget: the phase ancestors live in the workspace."""
+    """A tall image: 54 phases, a team of 14 workgroups."""
     log("forward tall")
     _check(synth.blob_image(3000, 1600, 3, seed=6), 1597)
 
