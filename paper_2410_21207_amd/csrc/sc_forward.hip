@@ -16,10 +16,10 @@
 //    its middle 240 (its core) are exact: every 8 rows the waves of a workgroup refresh the 8
 //    columns on each side of their cores from their neighbours' cores through LDS;
 //  * a workgroup computes the 976 columns of its 4 waves; in a team of several DP members, member
-//    g computes [g*S - K, g*S + S + K) and owns [g*S, g*S + S), S = 976 - 2K, and at the end of
-//    every phase of K = 56 rows it publishes its owned keys with the phase's tag and reads the keys
-//    of its outer K columns on each side once they carry that tag (bounded wait); an image of at
-//    most 968 columns has one DP member, whose columns from 0 are exact.
+//    g computes [g*S - X, g*S + S + X) and owns [g*S, g*S + S), S = 976 - 2X, X = 2K = 112, and
+//    at the end of every second phase of K = 56 rows it publishes its owned keys with the phase's
+//    tag and reads the keys of its outer X columns on each side once they carry that tag (bounded
+//    wait); an image of at most 968 columns has one DP member, whose columns from 0 are exact.
 // A member takes part in a seam's DP only while some of its owned columns are in the image, so
 // two neighbouring participants always wait for each other's keys at every phase end; with two
 // exchange rows (by phase parity) neither can then overwrite a row the other still has to read.
@@ -41,7 +41,9 @@ constexpr int XG = 8;                       // ghost columns on each side of a w
 constexpr int CORE = 64 * CPL - 2 * XG;     // 240 exact columns per wave
 constexpr int WIN = NW * CORE + 2 * XG;     // 976 columns a member computes
 constexpr int K = kFwtPhaseRows;            // 56 rows per phase
-constexpr int S = WIN - 2 * K;              // 864 columns a member of a multi-member team owns
+constexpr int XP = 2;                       // phases between two exchanges of the members' keys
+constexpr int X = XP * K;                   // 112 ghost columns on each side of a member's owned range
+constexpr int S = WIN - 2 * X;              // 752 columns a member of a multi-member team owns
 constexpr int PF = 8;                       // rows of pixels loaded ahead; also the LDS refresh period
 constexpr int GK = K / 4;                   // 4-row direction groups per phase
 constexpr int WD = 32;                      // window dwords per group: columns je-59 .. je+68
@@ -55,6 +57,7 @@ struct Smem {
     int jend[PMAX];
     unsigned long long red[NW];
     int flag;
+    int chain;  // jend[p] is final for every p >= chain
 };
 
 // tag of the keys published at global phase number n (seam k, phase p: n = k * P + p): 1..511,
@@ -82,7 +85,7 @@ __device__ __forceinline__ Cols member_cols(int rank, int gd) {
         c.own0 = 0;
         c.own1 = WIN - XG;  // columns from 0 are exact up to the last wave's right ghost
     } else {
-        c.base = rank * S - K;
+        c.base = rank * S - X;
         c.own0 = rank * S;
         c.own1 = rank * S + S;
     }
@@ -133,17 +136,18 @@ struct Carver {
         uint32_t Sk[CPL], Pup[CPL], dacc = 0;
         int phase = 0;
 
-        // end of a phase: the owned columns' ancestor offsets, then the exchange of the keys at the
-        // member's outer ghost columns (not after the last phase), then the offsets restart
+        // end of a phase: the owned columns' ancestor offsets, then (every XP phases, not after the
+        // last) the exchange of the keys at the member's outer ghost columns, then the offsets
+        // restart
         auto phase_end = [&]() {
             if (owned) {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
                     if (act[c]) *gp(ancg + (size_t)phase * d.W + j0 + c) = (uint8_t)(Sk[c] & 0x7Fu);
             }
-            if (gd > 1 && phase + 1 < P) {
+            if (gd > 1 && phase + 1 < P && phase % XP == XP - 1) {
                 const uint32_t tag = phase_tag(k * P + phase);
-                uint32_t* xr = xq + (size_t)(phase & 1) * d.xw + (j0 > 0 ? j0 : 0);
+                uint32_t* xr = xq + (size_t)((phase / XP) & 1) * d.xw + (j0 > 0 ? j0 : 0);
                 // every lane's publish comes before any lane's wait in program order
                 if (owned) {
                     const v4u o = {(Sk[0] & ~0x1FFu) | tag, (Sk[1] & ~0x1FFu) | tag, (Sk[2] & ~0x1FFu) | tag,
@@ -327,6 +331,9 @@ struct Carver {
             const int w = d.W - k;
             unsigned long long* amin = d.amk + (k & 1);
             const unsigned long long tm0 = timer ? wall_clock64() : 0ull;
+            // no phase end of this seam is known yet; the barriers of the DP and after it order this
+            // reset after every walker of the previous seam and before any of this one
+            if (t == 0) sm.chain = 0x7fffffff;
             // A member whose owned columns all lie beyond the current width has nothing to compute
             // (its ghost columns belong to its left neighbour) and takes no part in the exchange.
             // That keeps every exchange mutual: the left neighbour of a participating member always
@@ -346,21 +353,29 @@ struct Carver {
                 // reset before any member's minimum of seam k + 1
                 __hip_atomic_store(d.amk + ((k + 1) & 1), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // ---- backtrack, first hop (every member on its own): phase by phase
+            // ---- backtrack, first hop (every member on its own): thread 0 goes phase by phase
+            // through the ancestor offsets and publishes each phase end in LDS as soon as it is
+            // known; a wave starts on one of its phases once that phase's end is there, bottom
+            // phases first.  (sm.chain was set above every phase before the DP's barriers.)
             if (t == 0) {
                 int je = min(max((int)(key & 0xFFFFFFFFu), 0), w - 1);
                 sm.jend[P - 1] = je;
+                __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 for (int p = P - 1; p > 0; --p) {
                     const int a = (int)ld<true>(reinterpret_cast<const uint8_t*>(d.anc) + (size_t)p * d.W + je);
                     je = min(max(je + a - 64, 0), w - 1);
                     sm.jend[p - 1] = je;
+                    __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
-            __syncthreads();
             // ---- the rows of this member's phases (p = rank, rank + G, ...): one wave per phase
             // walks it from an LDS window of the direction map, then removes its rows
+            const int np = P > rank + G * wv ? (P - 1 - rank - G * wv) / (G * NW) + 1 : 0;  // phases of this wave
 #pragma unroll 1
-            for (int p = rank + G * wv; p < P; p += G * NW) {
+            for (int q = np - 1; q >= 0; --q) {
+                const int p = rank + G * wv + G * NW * q;
+                while (__hip_atomic_load(&sm.chain, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > p)
+                    __builtin_amdgcn_s_sleep(1);
                 const int r0 = p * K, n = min(K, H - r0), ng = (n + 3) >> 2;
                 const int je = sm.jend[p];
                 const int cb0 = max(0, je - (K - 1)) >> 2;

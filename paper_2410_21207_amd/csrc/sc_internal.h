@@ -114,13 +114,13 @@ constexpr size_t kFwdSlack = 256;
 
 // Forward-energy carve by teams of 256-thread workgroups on one XCD (sc_forward.hip).  A working
 // pixel is one dword.  Member g of a team with more than one DP member computes columns
-// [g*kFwtOwned - kFwtPhaseRows, (g+1)*kFwtOwned + kFwtPhaseRows) and owns [g*kFwtOwned,
+// [g*kFwtOwned - 2*kFwtPhaseRows, (g+1)*kFwtOwned + 2*kFwtPhaseRows) and owns [g*kFwtOwned,
 // (g+1)*kFwtOwned); a team of images up to kFwtSingle columns has one DP member.  blk: block ->
 // (image, member), or nullptr for one image whose members are blocks xcd, xcd + 8, ...
 constexpr int kFwtThreads = 256;
 constexpr int kFwtWindow = 976;  // 4 waves x 240 exact columns + 8 ghost columns on each side
 constexpr int kFwtPhaseRows = 56;
-constexpr int kFwtOwned = kFwtWindow - 2 * kFwtPhaseRows;
+constexpr int kFwtOwned = kFwtWindow - 4 * kFwtPhaseRows;  // keys exchanged every second phase
 constexpr int kFwtSingle = kFwtWindow - 8;  // widest image a single DP member carves
 hipError_t launch_fwt_prepare(const Img* imgs, int n, int max_rows, hipStream_t st);
 hipError_t launch_fwt_carve(const Img* imgs, const int2* blk, int nblocks, int xcd, hipStream_t st);
