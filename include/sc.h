@@ -364,6 +364,14 @@ sc_status sc_remove_object(const uint8_t* img, const uint8_t* mask, int H, int W
  *                  it started in this launch, or after max_seams seams; budget_us = 0 is
  *                  sc_slots_step.  A step's workgroups then stay busy for about the same time
  *                  instead of waiting for the one with the most work.
+ *   sc_slots_step_teams  sc_slots_step_timed where slot s is carved by a team of team[s]
+ *                  workgroups (host array of n_slots entries, 1 = one workgroup, at most 32);
+ *                  table_slots is the table's size as passed to sc_slot_table_bytes (>= n_slots):
+ *                  the teams sit on one XCD each and are resident together (a team that finds
+ *                  no room in this step carves with one workgroup); the budget is the team's
+ *                  first member's.  Results equal those of sc_slots_step_timed.  The call writes
+ *                  the step's block plan into the table (after the descriptors) with an
+ *                  asynchronous host-to-device copy from pageable memory.
  */
 size_t sc_slot_table_bytes(int n_slots);
 sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int n_slots, int slot,
@@ -372,6 +380,8 @@ sc_status sc_slot_clear(void* table, int n_slots, int slot, void* stream);
 sc_status sc_slots_step(const void* table, int n_slots, int max_seams, int32_t* progress, void* stream);
 sc_status sc_slots_step_timed(const void* table, int n_slots, int max_seams, long long budget_us, int32_t* progress,
                               void* stream);
+sc_status sc_slots_step_teams(const void* table, int table_slots, int n_slots, const int32_t* team, int max_seams,
+                              long long budget_us, int32_t* progress, void* stream);
 
 /*
  * Device-side status of the images of a workspace (synchronous: waits for the

@@ -84,6 +84,7 @@ SIGNATURES = {
     "sc_slot_clear": (I, [P, I, I, P]),
     "sc_slots_step": (I, [P, I, I, P, P]),
     "sc_slots_step_timed": (I, [P, I, I, ctypes.c_longlong, P, P]),
+    "sc_slots_step_teams": (I, [P, I, I, ctypes.POINTER(ctypes.c_int32), I, ctypes.c_longlong, P, P]),
 }
 
 _lib = None

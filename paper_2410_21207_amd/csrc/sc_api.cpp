@@ -42,7 +42,8 @@ struct WsHead {
 };
 constexpr uint32_t kMagic = sc::kWsMagic;
 static_assert(sizeof(WsHead) == sc::kWsHeadBytes, "header size");
-static_assert(sizeof(sc::Ctl) == 64, "ctl size");
+static_assert(sizeof(sc::Ctl) == 128, "ctl size");
+static_assert(sc::kWsImgOffset + sizeof(sc::Img) <= sc::kWsHeadBytes, "a single image's descriptor fits the header");
 
 constexpr int kMaxCostBound = 8388000;  // H*510*C: the column cost must fit 23 bits
 constexpr int kDefaultTeamSingle = 8;   // workgroups carving one image (sc_carve)
@@ -605,10 +606,16 @@ extern "C" int sc_read_stages(const void* ws, uint64_t* stages, int max_n) {
 
 // ---------------------------------------------------------------------------------- serving slots
 constexpr size_t kSlotBytes = sizeof(sc::Img);  // the table is a device array of descriptors
+constexpr int kMaxSlotTeam = 32;                // workgroups of one slot's team in a step
+
+// The table: the slots' descriptors, then room for the block plan of a step with teams (teams
+// laid out per XCD, then one block per slot).
+size_t slot_plan_offset(int n_slots) { return sc::align_up((size_t)n_slots * kSlotBytes, sc::kAlign); }
+size_t slot_plan_capacity(int n_slots) { return (size_t)8 * kMaxSlotTeam * n_slots + n_slots; }
 
 extern "C" size_t sc_slot_table_bytes(int n_slots) {
     if (n_slots < 1) return 0;
-    return sc::align_up((size_t)n_slots * kSlotBytes, sc::kAlign);
+    return slot_plan_offset(n_slots) + sc::align_up(slot_plan_capacity(n_slots) * sizeof(int4), sc::kAlign);
 }
 
 extern "C" sc_status sc_slot_start(const sc_job* job, void* ws, size_t ws_bytes, void* table, int n_slots, int slot,
@@ -654,8 +661,58 @@ extern "C" sc_status sc_slots_step_timed(const void* table, int n_slots, int max
     if (!table || n_slots < 1 || max_seams < 1 || budget_us < 0) return fail(SC_EINVAL, "bad slot step arguments");
     // the device wall clock runs at 100 MHz: 100 ticks per microsecond
     hipError_t e = sc::launch_carve_steps(static_cast<const sc::Img*>(table), n_slots, sc::default_variant(),
-                                          max_seams, (unsigned long long)budget_us * 100ull, progress,
+                                          max_seams, (unsigned long long)budget_us * 100ull, progress, nullptr, 0,
                                           (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "slot step");
+    return ok();
+}
+
+extern "C" sc_status sc_slots_step_teams(const void* table, int table_slots, int n_slots, const int32_t* team,
+                                         int max_seams, long long budget_us, int32_t* progress, void* stream) {
+    if (!table || !team || n_slots < 1 || max_seams < 1 || budget_us < 0)
+        return fail(SC_EINVAL, "bad slot step arguments");
+    if (table_slots < n_slots) return fail(SC_EINVAL, "n_slots=%d > table_slots=%d", n_slots, table_slots);
+    const int v = sc::default_variant();
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    // Teams first in the grid, each on one XCD, all of them resident at once (their members wait
+    // for each other); a team that finds no room carves with one workgroup.  Then one block per
+    // remaining slot (those need no company and may wait for a free slot of the device).
+    const int per_xcd = std::max(1, sc::carve_blocks_per_cu(v) * ncu / 8 * 3 / 4);
+    std::vector<int> order;
+    for (int s = 0; s < n_slots; ++s)
+        if (team[s] > 1) order.push_back(s);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return team[a] > team[b]; });
+    int used[8] = {0};
+    std::vector<int4> plan;
+    std::vector<char> single(n_slots, 1);
+    for (int s : order) {
+        const int G = std::min(team[s], kMaxSlotTeam);
+        int x = 0;
+        for (int c = 1; c < 8; ++c)
+            if (used[c] < used[x]) x = c;
+        if (used[x] + G > per_xcd) continue;
+        for (int r = 0; r < G; ++r) {
+            const size_t b = (size_t)x + 8 * (size_t)(used[x] + r);
+            if (plan.size() <= b) plan.resize(b + 1, make_int4(-1, 0, 0, 0));
+            plan[b] = make_int4(s, r, G, 0);
+        }
+        used[x] += G;
+        single[s] = 0;
+    }
+    for (int s = 0; s < n_slots; ++s)
+        if (single[s]) plan.push_back(make_int4(s, 0, 1, 0));
+    if (plan.size() > slot_plan_capacity(table_slots)) return fail(SC_EUNSUPPORTED, "step plan too large");
+    hipStream_t st = (hipStream_t)stream;
+    char* base = static_cast<char*>(const_cast<void*>(table));
+    // the plan goes after the descriptors of every slot of the table, so no descriptor is touched
+    int4* dplan = reinterpret_cast<int4*>(base + slot_plan_offset(table_slots));
+    e = hipMemcpyAsync(dplan, plan.data(), plan.size() * sizeof(int4), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = sc::launch_carve_steps(static_cast<const sc::Img*>(table), n_slots, v, max_seams,
+                                   (unsigned long long)budget_us * 100ull, progress, dplan, (int)plan.size(), st);
     if (e != hipSuccess) return hip_fail(e, "slot step");
     return ok();
 }

@@ -318,6 +318,8 @@ __device__ __forceinline__ void reset_ctl(const Img& d) {
     c->xmask = 0;
     c->done = 0;
     c->t_stage[0] = c->t_stage[1] = c->t_stage[2] = 0;
+    c->ebase = 0;
+    c->stop = 0;
 }
 
 // One source row as seen by a thread owning 4 pixels from column x0: the aligned dwords covering

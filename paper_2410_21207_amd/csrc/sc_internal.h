@@ -43,6 +43,11 @@ struct Ctl {
     unsigned xmask;                     // XCDs the team's workgroups ran on (bit per XCD)
     unsigned done;                      // seams removed so far (step-wise carving)
     unsigned long long t_stage[3];      // device clock spent in: DP sweep; backtrack + removal; band update
+    // step-wise carving by a team (serving): the barrier count the previous calls left, and the
+    // stop decision of the team's first member at the end of a seam
+    unsigned ebase;
+    unsigned stop;
+    unsigned pad[14];
 };
 constexpr unsigned kStatusTimeout = 1u;    // a team barrier timed out
 constexpr unsigned kStatusPlacement = 2u;  // a team's workgroups were not on one XCD
@@ -87,7 +92,7 @@ hipError_t launch_prepare_single(const Img& d, hipStream_t st);          // ener
 hipError_t launch_prepare_from_i32(const Img& d, const int32_t* energy, hipStream_t st);
 hipError_t launch_carve_single(const Img& d, int variant, int G, int xcd, hipStream_t st);
 hipError_t launch_carve_steps(const Img* table, int n, int variant, int max_seams, unsigned long long budget_ticks,
-                              int* progress, hipStream_t st);
+                              int* progress, const int4* plan, int nblocks, hipStream_t st);
 hipError_t launch_slot_write(Img* table, int slot, const Img& d, hipStream_t st);
 hipError_t launch_unpack_dirs(const Img& d, uint8_t* out, hipStream_t st);
 hipError_t launch_remove_seam(uint8_t* img, int H, int W, int C, long long pitch, const int32_t* seam,

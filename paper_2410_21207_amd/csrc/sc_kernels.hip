@@ -818,7 +818,13 @@ struct Carver {
                     if (s < w2) *gp(er + s) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s);
                 }
             }
+            // a team's time budget: its first member decides before the seam's last barrier, every
+            // member reads the decision after it
+            if (deadline && G > 1 && k + 1 < k_end && rank == 0 && threadIdx.x == 0)
+                __hip_atomic_store(&ctl->stop, wall_clock64() >= deadline ? 1u : 0u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
+            if (deadline && G > 1 && k + 1 < k_end && ld<true>(&ctl->stop)) k_end = k + 1;
             if (timer) {
                 const unsigned long long tm3 = wall_clock64();
                 ctl->t_stage[0] += tm1 - tm0;
@@ -860,10 +866,17 @@ struct Carver {
         const int k1 = max_seams > 0 ? min(nseams, k0 + max_seams) : nseams;
         if (k0 >= k1) return;
         if (rank == 0 && threadIdx.x == 0 && k0 == 0) ctl->t_begin = wall_clock64();
-        unsigned epoch = 0;
+        // a call that continues a carve (step mode) starts from the barrier count the previous
+        // calls left behind, so a team's barrier counter never has to be reset between launches
+        unsigned epoch = max_seams > 0 ? ld<true>(&ctl->ebase) : 0u;
         int kd = k0;  // seams removed in total when this call ends
         const bool team = G > 1 || d.W > kLdsExchangeMaxW;
         if (team) {
+            if (max_seams > 0) {
+                // keys published in an earlier step may carry any tag; the members clear the
+                // exchange rows (ordered before every DP by the barrier below)
+                for (int x = rank * NT + (int)threadIdx.x; x < 2 * d.xw; x += G * NT) *gp(d.xq + x) = 0u;
+            }
             // every member records its XCD; a team spread over several XCDs would not see each
             // other's stores through sc1 loads, so such an image is flagged instead of carved
             if (threadIdx.x == 0) __hip_atomic_fetch_or(&ctl->xmask, 1u << (xcc_id() & 31), __ATOMIC_RELAXED,
@@ -883,6 +896,11 @@ struct Carver {
         if (rank == 0 && threadIdx.x == 0) {
             ctl->done = (unsigned)kd;
             if (kd == nseams) ctl->t_end = wall_clock64();
+            if (max_seams > 0) {  // every member ended this call at the same barrier count
+                ctl->ebase = epoch;
+                ctl->xmask = 0;
+                ctl->stop = 0;
+            }
         }
     }
 };
@@ -915,30 +933,37 @@ __global__ __launch_bounds__(NT, 4) void carve_batch_kernel(const Img* __restric
     }
 }
 
-// Step-wise carve (serving): block b advances the image in slot b of the slot table by at most
-// max_seams seams (one workgroup per image) and reports how many seams it has removed in total
-// (-1 on a device error, -2 for an empty slot).  The table is a device array of descriptors
-// written by slot_start_kernel, so each block reads its descriptor with scalar loads.
+// Step-wise carve (serving): each image of the slot table advances by at most max_seams seams and
+// reports how many seams it has removed in total (-1 on a device error, -2 for an empty slot).
+// Without a plan block b carves slot b alone; with one, block b is member plan[b].y of the team of
+// plan[b].z workgroups that carves slot plan[b].x (-1: no work), the members of a team on one XCD.
+// The table is a device array of descriptors written by slot_write_kernel.
 template <int CPL, int KR, int NT>
 __global__ __launch_bounds__(NT, 4) void carve_steps_kernel(const Img* __restrict__ table, int n, int max_seams,
                                                             unsigned long long budget_ticks,
-                                                            int* __restrict__ progress) {
+                                                            int* __restrict__ progress, const int4* __restrict__ plan) {
     using CV = Carver<CPL, KR, NT>;
     __shared__ typename CV::Smem sm;
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const Img d = table[b];
+    int slot = (int)blockIdx.x, rank = 0, G = 1;
+    if (plan) {
+        const int4 p = plan[blockIdx.x];
+        slot = p.x;
+        rank = p.y;
+        G = p.z;
+    }
+    if (slot < 0 || slot >= n) return;
+    const Img d = table[slot];
     if (d.H == 0) {
-        if (threadIdx.x == 0 && progress) progress[b] = -2;
+        if (rank == 0 && threadIdx.x == 0 && progress) progress[slot] = -2;
         return;
     }
-    // a time budget (device wall clock ticks) ends the workgroup's share after the seam that
-    // crosses it, so a step's workgroups stay busy for about the same time
-    CV::carve_image(d, 0, 1, sm, max_seams, budget_ticks ? wall_clock64() + budget_ticks : 0ull);
+    // a time budget (device wall clock ticks) ends the image's share after the seam that crosses
+    // it, so a step's workgroups stay busy for about the same time
+    CV::carve_image(d, rank, G, sm, max_seams, budget_ticks ? wall_clock64() + budget_ticks : 0ull);
     __syncthreads();
-    if (threadIdx.x == 0 && progress) {
+    if (rank == 0 && threadIdx.x == 0 && progress) {
         const Ctl* ctl = reinterpret_cast<const Ctl*>(d.amin);
-        progress[b] = (ctl->status & (kStatusTimeout | kStatusPlacement)) ? -1 : (int)ctl->done;
+        progress[slot] = (ctl->status & (kStatusTimeout | kStatusPlacement)) ? -1 : (int)ctl->done;
     }
 }
 
@@ -1067,12 +1092,13 @@ hipError_t launch_carve_batch(const Img* imgs, const int2* blk, const int2* team
 }
 
 hipError_t launch_carve_steps(const Img* table, int n, int v, int max_seams, unsigned long long budget_ticks,
-                              int* progress, hipStream_t st) {
+                              int* progress, const int4* plan, int nblocks, hipStream_t st) {
+    const int nb = plan ? nblocks : n;
     switch (v) {
 #define X(id, c, k, t)                                                                                        \
     case id:                                                                                                  \
-        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(n), dim3(t), 0, st, table, n, max_seams, budget_ticks, \
-                           progress);                                                                              \
+        hipLaunchKernelGGL((carve_steps_kernel<c, k, t>), dim3(nb), dim3(t), 0, st, table, n, max_seams, budget_ticks, \
+                           progress, plan);                                                                        \
         break;
         SC_VARIANTS(X)
 #undef X

@@ -5,7 +5,9 @@ as a slot and enough of the HBM budget are free, keeps every admitted image and 
 on the device between seams, and advances ALL admitted images together: one step is one launch
 of the step kernel (``sc_slots_step_timed``), one workgroup per image, in which every active
 image removes seams until the step's time budget is spent (or ``seams_per_step`` seams): small
-requests finish within a step and no workgroup waits for the largest one.  A request that
+requests finish within a step and no workgroup waits for the largest one.  With a team policy
+(``sc_slots_step_teams``) a request with much work left advances with a team of workgroups on
+one XCD instead of one, so the largest requests no longer set the tail latency.  A request that
 arrives while others are mid-carve joins at the next step; its work overlaps theirs on the
 device.  Latency is arrival to completion.
 
@@ -25,7 +27,7 @@ import time
 from collections import deque
 from dataclasses import dataclass, field
 
-__all__ = ["Ticket", "Server", "GPUExecutor", "percentile"]
+__all__ = ["Ticket", "Server", "GPUExecutor", "percentile", "team_by_work"]
 
 
 @dataclass
@@ -42,6 +44,7 @@ class Ticket:
     done: float | None = None
     status: str = "queued"   # queued | running | done | error | rejected
     slot: int = -1
+    seams_done: int = 0
     state_bytes: int = 0
     result: object = None
     error: str = ""
@@ -60,6 +63,21 @@ class Ticket:
         return None if self.done is None else self.done - self.arrival
 
 
+def team_by_work(min_pixel_seams: float = 4e8, max_team: int = 16):
+    """A team policy: a request with at least `min_pixel_seams` of work left gets one workgroup per
+    eight 144-column DP strips of its current width, doubled for the removal (2 .. max_team);
+    every other request one workgroup."""
+    def policy(t: "Ticket") -> int:
+        r = t.seams - t.seams_done
+        wc = t.w - t.seams_done
+        left = t.h * r * (wc - (r - 1) / 2.0)
+        if left < min_pixel_seams:
+            return 1
+        strips = -(-wc // 144)
+        return int(min(max_team, max(2, 2 * -(-strips // 8))))
+    return policy
+
+
 def percentile(xs, q):
     """Linear-interpolated percentile of a non-empty list (q in [0, 100])."""
     xs = sorted(xs)
@@ -75,12 +93,13 @@ class Server:
     """FIFO admission by HBM budget and free slots; continuous batching of the carve steps."""
 
     def __init__(self, executor, budget_bytes: int = 64 << 30, max_slots: int = 256, seams_per_step: int = 16,
-                 clock=time.perf_counter, step_budget_us: int = 0):
+                 clock=time.perf_counter, step_budget_us: int = 0, team_policy=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.seams_per_step = int(seams_per_step)
         self.step_budget_us = int(step_budget_us)  # > 0: steps end on time, seams_per_step is a cap
+        self.team_policy = team_policy  # ticket -> workgroups carving it in the next step, or None
         self.clock = clock
         self.queue: deque[Ticket] = deque()
         self.active: dict[int, Ticket] = {}
@@ -137,13 +156,22 @@ class Server:
         if not self.active:
             return []
         n = max(self.active) + 1
-        progress = (self.ex.advance(n, self.seams_per_step, self.step_budget_us) if self.step_budget_us
-                    else self.ex.advance(n, self.seams_per_step))
+        if self.team_policy is not None:
+            teams = [1] * n
+            for slot, t in self.active.items():
+                teams[slot] = max(1, int(self.team_policy(t)))
+            progress = self.ex.advance(n, self.seams_per_step, self.step_budget_us, teams)
+        elif self.step_budget_us:
+            progress = self.ex.advance(n, self.seams_per_step, self.step_budget_us)
+        else:
+            progress = self.ex.advance(n, self.seams_per_step)
         self.steps += 1
         now = self.clock()
         finished = []
         for slot, t in list(self.active.items()):
             p = progress[slot]
+            if p >= 0:
+                t.seams_done = p
             if p < 0:
                 self._retire(t, now, "error", f"device status {p}")
                 finished.append(t)
@@ -255,9 +283,17 @@ class GPUExecutor:
                   ctypes.c_void_p(self.table.data_ptr()), self.max_slots, slot,
                   ctypes.c_void_p(self.stream.cuda_stream))
 
-    def advance(self, n, max_seams, budget_us: int = 0):
-        self._lib.call("sc_slots_step_timed", ctypes.c_void_p(self.table.data_ptr()), n, max_seams, int(budget_us),
-                       ctypes.c_void_p(self.progress.data_ptr()), ctypes.c_void_p(self.stream.cuda_stream))
+    def advance(self, n, max_seams, budget_us: int = 0, teams=None):
+        if teams is None:
+            self._lib.call("sc_slots_step_timed", ctypes.c_void_p(self.table.data_ptr()), n, max_seams,
+                           int(budget_us), ctypes.c_void_p(self.progress.data_ptr()),
+                           ctypes.c_void_p(self.stream.cuda_stream))
+        else:
+            arr = (ctypes.c_int32 * n)(*[int(g) for g in teams[:n]])
+            self._lib.call("sc_slots_step_teams", ctypes.c_void_p(self.table.data_ptr()), self.max_slots, n, arr,
+                           max_seams,
+                           int(budget_us), ctypes.c_void_p(self.progress.data_ptr()),
+                           ctypes.c_void_p(self.stream.cuda_stream))
         with self.torch.cuda.stream(self.stream):  # ordered after the step on the same stream
             self.progress_host[:n].copy_(self.progress[:n], non_blocking=True)
         self.stream.synchronize()
@@ -283,6 +319,8 @@ def main():
     ap.add_argument("--step-us", type=int, default=20000,
                     help="time budget of a step in microseconds (0: every slot removes seams-per-step seams)")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--teams", action="store_true",
+                    help="requests with much work left advance with a team of workgroups (team_by_work)")
     args = ap.parse_args()
 
     import torch
@@ -298,14 +336,15 @@ def main():
 
     srv = Server(GPUExecutor(args.slots, dev), budget_bytes=int(args.budget_gb * 1e9),
                  max_slots=args.slots,
-                 seams_per_step=args.seams_per_step, step_budget_us=args.step_us)
+                 seams_per_step=args.seams_per_step, step_budget_us=args.step_us,
+                 team_policy=team_by_work() if args.teams else None)
     st = srv.run(reqs, payload, progress=lambda m: print(m, file=sys.stderr, flush=True))
     offered = sum(r.h * ((r.w - r.target_w) * r.w - (r.w - r.target_w) * (r.w - r.target_w - 1) // 2)
                   for r in reqs) / args.duration
     st.update({"workload": f"Poisson {args.rate}/s for {args.duration}s, sides log-uniform [128,4096], "
                            "target 50-90% of width, 64 GB budget",
                "offered_pixel_seams_per_s": round(offered, 1), "seams_per_step": args.seams_per_step,
-               "step_us": args.step_us,
+               "step_us": args.step_us, "teams": bool(args.teams),
                "slots": args.slots})
     print(json.dumps(st), flush=True)
 

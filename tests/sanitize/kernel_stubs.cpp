@@ -14,7 +14,9 @@ hipError_t launch_energy_i32(const uint8_t*, int, int, int, long long, int32_t*,
 hipError_t launch_prepare_single(const Img&, hipStream_t) { return kNo; }
 hipError_t launch_prepare_from_i32(const Img&, const int32_t*, hipStream_t) { return kNo; }
 hipError_t launch_carve_single(const Img&, int, int, int, hipStream_t) { return kNo; }
-hipError_t launch_carve_steps(const Img*, int, int, int, unsigned long long, int*, hipStream_t) { return kNo; }
+hipError_t launch_carve_steps(const Img*, int, int, int, unsigned long long, int*, const int4*, int, hipStream_t) {
+    return kNo;
+}
 hipError_t launch_slot_write(Img*, int, const Img&, hipStream_t) { return kNo; }
 hipError_t launch_unpack_dirs(const Img&, uint8_t*, hipStream_t) { return kNo; }
 hipError_t launch_remove_seam(uint8_t*, int, int, int, long long, const int32_t*, hipStream_t) { return kNo; }

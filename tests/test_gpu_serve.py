@@ -8,7 +8,7 @@ import oracle
 import synth
 from gpu_helpers import dev, host, log
 from paper_2410_21207_amd import api
-from paper_2410_21207_amd.serve import GPUExecutor, Server
+from paper_2410_21207_amd.serve import GPUExecutor, Server, team_by_work
 
 pytestmark = pytest.mark.gpu
 
@@ -24,13 +24,20 @@ def _requests(n, seed):
     return out
 
 
-@pytest.mark.parametrize("seams_per_step,step_us", [(1, 0), (7, 0), (1 << 20, 300)])
-def test_served_in_mix_equals_alone(seams_per_step, step_us):
-    reqs = _requests(24, seed=seams_per_step % 1000 + step_us)
-    log("serve mix", seams_per_step, step_us)
+def _teams_for_tests(t):
+    """Team slots for the small test requests: 2 to 4 workgroups by width, changing as they shrink."""
+    wc = t.w - t.seams_done
+    return 1 if wc < 120 else min(4, 2 + wc // 200)
+
+
+@pytest.mark.parametrize("seams_per_step,step_us,teams", [(1, 0, False), (7, 0, False), (1 << 20, 300, False),
+                                                          (3, 0, True), (1 << 20, 300, True)])
+def test_served_in_mix_equals_alone(seams_per_step, step_us, teams):
+    reqs = _requests(24, seed=seams_per_step % 1000 + step_us + (7 if teams else 0))
+    log("serve mix", seams_per_step, step_us, "teams" if teams else "")
     budget = 6 * max(2 * img.nbytes for img, _ in reqs) + 8 * (1 << 20)
     srv = Server(GPUExecutor(16), budget_bytes=budget, max_slots=16, seams_per_step=seams_per_step,
-                 step_budget_us=step_us)
+                 step_budget_us=step_us, team_policy=_teams_for_tests if teams else None)
     ts = [srv.submit(img.shape[0], img.shape[1], 3, tw, dev(img)) for img, tw in reqs]
     while not srv.idle():
         srv.step()
@@ -44,6 +51,29 @@ def test_served_in_mix_equals_alone(seams_per_step, step_us):
             assert np.array_equal(host(seams), host(a_seams)) and np.array_equal(host(costs), host(a_costs))
         if i % 6 == 0:
             assert np.array_equal(host(out), oracle.carve(img, tw)[0])
+
+
+def test_team_steps_leave_empty_slots_empty():
+    """A team step over the first few slots, then a step over more slots that include emptied ones:
+    the block plan of the first step must not have touched any slot's descriptor (the emptied slots
+    report -2 and the live ones carve correctly)."""
+    from paper_2410_21207_amd.serve import Ticket
+    ex = GPUExecutor(12)
+    imgs = [synth.blob_image(60 + 7 * i, 150 + 11 * i, 3, seed=300 + i) for i in range(8)]
+    tickets = [Ticket(i, im.shape[0], im.shape[1], 3, im.shape[1] - 20, 0.0, dev(im)) for i, im in enumerate(imgs)]
+    for i in range(6):
+        ex.start(i, tickets[i])
+    for i in range(2, 6):  # four slots emptied again
+        ex.release(i)
+    p = ex.advance(2, 3, 0, [3, 2])  # the plan of this step lies beyond all 12 descriptors
+    assert p[0] == 3 and p[1] == 3
+    ex.start(7, tickets[7])
+    p = ex.advance(8, 1 << 20, 0, [2, 1, 1, 1, 1, 1, 1, 4])
+    assert p[2:7] == [-2] * 5 and p[0] == 20 and p[1] == 20 and p[7] == 20
+    for i in (0, 1, 7):
+        out, seams, costs = ex.result(i)
+        a_out, a_seams, a_costs = api.carve(dev(imgs[i]), imgs[i].shape[1] - 20)
+        assert np.array_equal(host(out), host(a_out)) and np.array_equal(host(seams), host(a_seams))
 
 
 def test_open_loop_serving_short():

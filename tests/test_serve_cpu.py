@@ -160,3 +160,10 @@ def test_open_loop_run_with_virtual_time():
     for t, r in zip(srv.tickets, arrivals):
         assert np.array_equal(t.result[0], oracle.carve(r.img, r.target_w)[0])
 
+
+def test_team_policy_sizes():
+    from paper_2410_21207_amd.serve import Ticket, team_by_work
+    pol = team_by_work(min_pixel_seams=1e6, max_team=16)
+    assert pol(Ticket(0, 100, 100, 3, 90, 0.0)) == 1                     # little work left
+    assert pol(Ticket(1, 4096, 4096, 3, 2048, 0.0)) == 8                 # 29 strips: 4 x 2
+    assert pol(Ticket(2, 2000, 1000, 3, 500, 0.0)) == 2
