@@ -31,9 +31,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 METRIC = "pixel-seams removed/sec + HBM GB/s %peak; p50/p99 carve latency, batched vs plain"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "carve_batch_c4_traffic.json")
-FWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_carve_batch_traffic.json")
+FWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwt_carve_batch_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2410_21207_amd", "csrc", f)
-                  for f in ("sc_kernels.hip", "sc_device.h", "sc_internal.h")]
+                  for f in ("sc_kernels.hip", "sc_forward.hip", "sc_object.hip", "sc_device.h", "sc_internal.h")]
 
 
 def log(*a):
@@ -761,9 +761,10 @@ def cpu_baseline(jobs, imgs_np, gpu_results, seconds, forward=False, must=()):
             agree["costs"] &= bool(np.array_equal(o[2], g_costs.cpu().numpy()))
         agree["pixels"] &= bool(np.array_equal(o[0], g_out.cpu().numpy()))
     crit = ", ".join(f"{jobs[i].w}x{jobs[i].h}" for i in dict.fromkeys(int(i) for i in must))
+    order = f"the critical image(s) {crit}, then job order" if must else "job order"
     return {"value": round(acc / dt, 1), "unit": "pixel-seams/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(idx)} of the {len(jobs)} batch images (the critical image(s) {crit}, then job "
-                      f"order up to ~{seconds:.0f}s per core), full carves, one image per thread, {dt:.1f}s wall",
+            "sample": f"{len(idx)} of the {len(jobs)} batch images ({order} up to ~{seconds:.0f}s per core), "
+                      f"full carves, one image per thread, {dt:.1f}s wall",
             "seams_match_gpu": agree["seams"], "costs_match_gpu": agree["costs"],
             "pixels_match_gpu": agree["pixels"]}
 
