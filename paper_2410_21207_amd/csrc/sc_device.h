@@ -44,6 +44,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufWord3);
 }
 
+// A dword at a lane's byte offset into a buffer; COH sets the sc1 bit (the load reads the XCD's L2,
+// like ld<true>).  Being a plain load, it leaves the compiler's memory-counter waits for later
+// loads exact, where an atomic load in flight makes it wait for every outstanding access.
+template <bool COH>
+__device__ __forceinline__ uint32_t buf_ld32(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, COH ? 16 : 0);
+}
+
 __device__ __forceinline__ uint32_t xcc_id() {
     uint32_t v;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
@@ -285,18 +293,18 @@ __device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, 
         __syncthreads();
         if (threadIdx.x == 0) {
             epoch += (unsigned)G;
-            __hip_atomic_fetch_add(d.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gp(d.bar), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long t0 = wall_clock64();
             int ab = 0;
-            while (__hip_atomic_load(d.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            while (__hip_atomic_load(gp(d.bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
                 __builtin_amdgcn_s_sleep(1);
-                if (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                if (__hip_atomic_load(gp(d.status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                     (kStatusTimeout | kStatusPlacement)) {
                     ab = 1;
                     break;
                 }
                 if (wall_clock64() - t0 > 1000000000ull) {  // 10 s at the 100 MHz constant clock
-                    __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_or(gp(d.status), kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ab = 1;
                     break;
                 }
@@ -310,7 +318,7 @@ __device__ __forceinline__ bool team_sync(const Img& d, unsigned& epoch, int G, 
 
 // Reset the control words of one image (every carve launch starts from them).
 __device__ __forceinline__ void reset_ctl(const Img& d) {
-    Ctl* c = reinterpret_cast<Ctl*>(d.amin);
+    GAS Ctl* c = gp(reinterpret_cast<Ctl*>(d.amin));
     c->amin = ~0ull;
     c->bar = 0;
     c->status = 0;

@@ -175,9 +175,9 @@ struct Carver {
                             const unsigned long long now = wall_clock64();
                             if (t0 == 0) t0 = now;
                             if (now - t0 > 1000000000ull ||
-                                (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                                (__hip_atomic_load(gp(d.status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                                  (kStatusTimeout | kStatusPlacement))) {
-                                __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED,
+                                __hip_atomic_fetch_or(gp(d.status), kStatusTimeout, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
                                 break;
                             }
@@ -298,7 +298,7 @@ struct Carver {
         if (t == 0) {
             unsigned long long b = sm.red[0];
             for (int x = 1; x < NW; ++x) b = min(b, sm.red[x]);
-            if (b != ~0ull) atomicMin(amin, b);
+            if (b != ~0ull) __hip_atomic_fetch_min(gp(amin), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -307,7 +307,7 @@ struct Carver {
         const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
         const int H = d.H, nseams = d.W - d.target_w, P = (H + K - 1) / K;
         const int gd = dp_members(d.W);
-        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        GAS Ctl* ctl = gp(reinterpret_cast<Ctl*>(d.amin));
         const bool timer = rank == 0 && t == 0;
         unsigned epoch = 0;
         if (G > 1) {
@@ -318,7 +318,7 @@ struct Carver {
             const unsigned m = __hip_atomic_load(&ctl->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (__popc(m) != 1) {
                 if (t == 0)
-                    __hip_atomic_fetch_or(d.status, kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_or(gp(d.status), kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return;
             }
         } else {
@@ -346,12 +346,12 @@ struct Carver {
                 __syncthreads();
             }
             const unsigned long long tm1 = timer ? wall_clock64() : 0ull;
-            const unsigned long long key = __hip_atomic_load(amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long key = __hip_atomic_load(gp(amin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (rank == 0 && t == 0) {
                 if (d.costs_out) *gp(d.costs_out + k) = (long long)(key >> 32);
                 // the next seam's argmin word; the team barrier after the removal orders this
                 // reset before any member's minimum of seam k + 1
-                __hip_atomic_store(d.amk + ((k + 1) & 1), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gp(d.amk + ((k + 1) & 1)), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             // ---- backtrack, first hop (every member on its own): thread 0 goes phase by phase
             // through the ancestor offsets and publishes each phase end in LDS as soon as it is
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(256) void fwt_prepare_kernel(const Img* __restrict_
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) {
             reset_ctl(d);
-            d.amk[0] = d.amk[1] = ~0ull;
+            *gp(d.amk) = *gp(d.amk + 1) = ~0ull;
         }
         for (int x = threadIdx.x; x < 2 * d.xw; x += blockDim.x) *gp(d.xq + x) = 0u;
     }

@@ -465,8 +465,9 @@ struct Carver {
         // start offsets of this item's rows and of the next item's rows: lane l holds row r0 + l.
         // A preloaded item got its own from the previous item, so its first prefetch does not wait.
         const int last = d.H - 1;
-        const int rov = preloaded ? rovc : lane < KR ? ld<TEAM>(d.ro + min(r0 + lane, last)) : 0;
-        const int rovn = lane < KR ? ld<TEAM>(d.ro + min(nx.r0 + lane, last)) : 0;
+        const __amdgpu_buffer_rsrc_t rro = make_rsrc(d.ro, (uint32_t)d.H * 4u);
+        const int rov = preloaded ? rovc : (int)buf_ld32<TEAM>(rro, lane < KR ? (uint32_t)min(r0 + lane, last) * 4u : kBufDrop);
+        const int rovn = (int)buf_ld32<TEAM>(rro, lane < KR ? (uint32_t)min(nx.r0 + lane, last) * 4u : kBufDrop);
         rovc = rovn;
         // byte offset in the energy plane of row r0 + l (row base plus the row's start offset) in
         // lane l, rows past the image clamped to the last one; a row's scalar buffer offset is
@@ -511,10 +512,10 @@ struct Carver {
                         const unsigned long long now = wall_clock64();
                         if (t0 == 0) t0 = now;
                         if (now - t0 > 1000000000ull ||
-                            (__hip_atomic_load(d.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                            (__hip_atomic_load(gp(d.status), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
                              (kStatusTimeout | kStatusPlacement))) {
                             if (lane == 0)
-                                __hip_atomic_fetch_or(d.status, kStatusTimeout, __ATOMIC_RELAXED,
+                                __hip_atomic_fetch_or(gp(d.status), kStatusTimeout, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
                             return false;
                         }
@@ -562,6 +563,22 @@ struct Carver {
             }
         };
 
+        // A full block of PF rows stores its two 4-row groups together at its end: a store between
+        // the prefetches would make the wait for the next block's first row cover the loads
+        // issued after it (one vector memory counter for loads and stores, drained in order).
+        uint32_t gk0 = 0, gk1 = 0;  // the block's first group
+        auto flush_block = [&](int rb) {
+            const uint32_t g0 = (uint32_t)(rb >> 2) * gbytes;
+            if constexpr (CPL == 4) {
+                __builtin_amdgcn_raw_buffer_store_b32(gk0, rdir, (int)doff, (int)g0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(pk0, rdir, (int)doff, (int)(g0 + gbytes), 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b64((v2u){gk0, gk1}, rdir, (int)doff, (int)g0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64((v2u){pk0, pk1}, rdir, (int)doff, (int)(g0 + gbytes), 0);
+            }
+        };
+        static_assert(PF == 8, "a block is two direction groups");
+
         int rb = r0;  // r0 and every block start are multiples of 4, so groups never straddle blocks
         // blocks whose prefetch targets stay inside this item
         for (; rb + 2 * PF <= r1; rb += PF) {
@@ -569,8 +586,10 @@ struct Carver {
             for (int i = 0; i < PF; ++i) {  // the slot is refilled after its row (no register copy)
                 step(rb + i, ring[i]);
                 ring[i] = load_ev<TEAM>(re, soff(rb - r0 + i + PF), eoff);
-                if ((i & 3) == 3) flush(rb + i);
+                __builtin_amdgcn_sched_barrier(0);  // keep the prefetch PF rows ahead of its use
+                if (i == 3) gk0 = pk0, gk1 = pk1;
             }
+            flush_block(rb);
         }
         // the last full block prefetches the next item's first rows, or else this item's partial
         // tail (rows past the item's end are clamped to its last row and never stepped)
@@ -580,8 +599,10 @@ struct Carver {
                 step(rb + i, ring[i]);
                 ring[i] = load_ev<TEAM>(re, cross ? soffn(i) : soff(min(rb - r0 + PF + i, r1 - 1 - r0)),
                                         cross ? nx.off : eoff);
-                if ((i & 3) == 3) flush(rb + i);
+                __builtin_amdgcn_sched_barrier(0);
+                if (i == 3) gk0 = pk0, gk1 = pk1;
             }
+            flush_block(rb);
             rb += PF;
         }
         // the rows of a partial last phase (the next item then loads its own first rows)
@@ -626,7 +647,7 @@ struct Carver {
                 const unsigned long long o = __shfl_xor(key, off, 64);
                 key = o < key ? o : key;
             }
-            if (lane == 0 && key != ~0ull) atomicMin(d.amin, key);
+            if (lane == 0 && key != ~0ull) __hip_atomic_fetch_min(gp(d.amin), key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return true;
     }
@@ -644,7 +665,7 @@ struct Carver {
         const int rpw = (d.H + TW - 1) / TW;
         const int ra = min(d.H, tw * rpw), rb = min(d.H, ra + rpw);  // rows this wave owns
         const int H = d.H, P = d.P;
-        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        GAS Ctl* ctl = gp(reinterpret_cast<Ctl*>(d.amin));
         const bool timer = rank == 0 && threadIdx.x == 0;  // one clock reader per image
         unsigned long long tm0 = 0, tm1 = 0, tm2 = 0;
         for (int k = k_begin; k < k_end; ++k) {
@@ -682,7 +703,7 @@ struct Carver {
                 if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
             }
             if (timer) tm1 = wall_clock64();
-            const unsigned long long key = __hip_atomic_load(d.amin, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long key = __hip_atomic_load(gp(d.amin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int jstar = min(max((int)(key & 0xffffffffu), 0), w - 1);
             if (rank == 0 && threadIdx.x == 0 && d.costs_out) *gp(d.costs_out + k) = (long long)(key >> 32);
             // ---- backtrack (a5): thread 0 hops from phase end to phase end and publishes the seam
@@ -801,7 +822,7 @@ struct Carver {
             if (timer) tm2 = wall_clock64();
             if (d.mode) break;
             if (rank == 0 && threadIdx.x == 0)
-                __hip_atomic_store(d.amin, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gp(d.amin), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // ---- band energy (a2): only the new columns s-1 and s of each row changed
             const int w2 = w - 1;
             for (int rc = ra; rc < rb; rc += 64) {
@@ -824,7 +845,7 @@ struct Carver {
                 __hip_atomic_store(&ctl->stop, wall_clock64() >= deadline ? 1u : 0u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             if (!team_sync<TEAM>(d, epoch, G, &sm.flag)) return k;
-            if (deadline && G > 1 && k + 1 < k_end && ld<true>(&ctl->stop)) k_end = k + 1;
+            if (deadline && G > 1 && k + 1 < k_end && __hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) k_end = k + 1;
             if (timer) {
                 const unsigned long long tm3 = wall_clock64();
                 ctl->t_stage[0] += tm1 - tm0;
@@ -860,7 +881,7 @@ struct Carver {
     // Carve one image, or (max_seams > 0) continue it by at most max_seams seams.
     static __device__ __forceinline__ void carve_image(const Img& d, int rank, int G, Smem& sm, int max_seams,
                                                        unsigned long long deadline = 0) {
-        Ctl* ctl = reinterpret_cast<Ctl*>(d.amin);
+        GAS Ctl* ctl = gp(reinterpret_cast<Ctl*>(d.amin));
         const int nseams = d.mode ? 1 : d.W - d.target_w;
         const int k0 = max_seams > 0 ? (int)ctl->done : 0;
         const int k1 = max_seams > 0 ? min(nseams, k0 + max_seams) : nseams;
@@ -868,7 +889,7 @@ struct Carver {
         if (rank == 0 && threadIdx.x == 0 && k0 == 0) ctl->t_begin = wall_clock64();
         // a call that continues a carve (step mode) starts from the barrier count the previous
         // calls left behind, so a team's barrier counter never has to be reset between launches
-        unsigned epoch = max_seams > 0 ? ld<true>(&ctl->ebase) : 0u;
+        unsigned epoch = max_seams > 0 ? __hip_atomic_load(&ctl->ebase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
         int kd = k0;  // seams removed in total when this call ends
         const bool team = G > 1 || d.W > kLdsExchangeMaxW;
         if (team) {
@@ -885,7 +906,7 @@ struct Carver {
             const unsigned m = __hip_atomic_load(&ctl->xmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (__popc(m) != 1) {
                 if (threadIdx.x == 0)
-                    __hip_atomic_fetch_or(d.status, kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_or(gp(d.status), kStatusPlacement, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return;
             }
             kd = carve_seams<true>(d, rank, G, sm, k0, k1, epoch, deadline);
@@ -962,7 +983,7 @@ __global__ __launch_bounds__(NT, 4) void carve_steps_kernel(const Img* __restric
     CV::carve_image(d, rank, G, sm, max_seams, budget_ticks ? wall_clock64() + budget_ticks : 0ull);
     __syncthreads();
     if (rank == 0 && threadIdx.x == 0 && progress) {
-        const Ctl* ctl = reinterpret_cast<const Ctl*>(d.amin);
+        const GAS Ctl* ctl = gp(reinterpret_cast<const Ctl*>(d.amin));
         progress[slot] = (ctl->status & (kStatusTimeout | kStatusPlacement)) ? -1 : (int)ctl->done;
     }
 }

@@ -69,7 +69,7 @@ struct Carver : PixRow<C, CPL> {
     static __device__ __forceinline__ void carve(const ObjImg& d, Smem& sm, uint8_t* anc_lds) {
         const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
         const int H = d.H, W = d.W, j0 = t * CPL;
-        ObjCtl* ctl = d.ctl;
+        GAS ObjCtl* ctl = gp(d.ctl);
         if (t == 0) ctl->t_begin = wall_clock64();
         const long long bias = (long long)H * 510 * C + 1;
 
