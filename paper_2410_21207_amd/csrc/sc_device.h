@@ -52,6 +52,11 @@ __device__ __forceinline__ uint32_t buf_ld32(__amdgpu_buffer_rsrc_t r, uint32_t 
     return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, COH ? 16 : 0);
 }
 
+template <bool COH>
+__device__ __forceinline__ uint8_t buf_ld8(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, 0, COH ? 16 : 0);
+}
+
 __device__ __forceinline__ uint32_t xcc_id() {
     uint32_t v;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
@@ -100,38 +105,43 @@ __device__ __forceinline__ SSeg sseg(uint8_t* lo, uint8_t* hi, int sh) {
 }
 
 // W[u] holds 20 loaded bytes: left = the slot then the dword above, right = the dword below then
-// the slot.
+// the slot.  The accesses are buffer loads and stores through a descriptor starting 16 bytes below
+// the segment's first slot, so every offset is non-negative; a lane without a slot, or without a
+// neighbour dword to read, gets a dropped offset (its load returns 0, its store writes nothing).
+// With no branches around them, all loads of a pass go out before the first wait.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sseg_rsrc(const SSeg& g) {
+    return make_rsrc(g.base - 16, (uint32_t)(g.n + 2) * 16u);
+}
+
 template <int U, bool R>
 __device__ __forceinline__ void sseg_load(const SSeg& g, int fb, int lane, uint32_t (&W)[U][5]) {
+    const __amdgpu_buffer_rsrc_t r = sseg_rsrc(g);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) W[u][i] = 0;
         const int f = fb + u * 64 + lane;
-        if (f < g.n) {
-            const int so = (R ? g.n - 1 - f : f) << 4;
-            const uint8_t* sp = g.base + so;
-            const uint64_t v0 = *gp(reinterpret_cast<const uint64_t*>(sp));
-            const uint64_t v1 = *gp(reinterpret_cast<const uint64_t*>(sp) + 1);
-            constexpr int k = R ? 1 : 0;
-            W[u][k + 0] = (uint32_t)v0; W[u][k + 1] = (uint32_t)(v0 >> 32);
-            W[u][k + 2] = (uint32_t)v1; W[u][k + 3] = (uint32_t)(v1 >> 32);
-            if (R) {
-                if (so > g.q0 - g.sh) W[u][0] = *gp(reinterpret_cast<const uint32_t*>(sp - 4));
-            } else {
-                if (so + 16 - g.sh < g.q1) W[u][4] = *gp(reinterpret_cast<const uint32_t*>(sp + 16));
-            }
+        const bool in = f < g.n;
+        const int so = (R ? g.n - 1 - f : f) << 4;
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(in ? (uint32_t)so + 16u : kBufDrop), 0, 0);
+        constexpr int k = R ? 1 : 0;
+        W[u][k + 0] = v[0]; W[u][k + 1] = v[1];
+        W[u][k + 2] = v[2]; W[u][k + 3] = v[3];
+        if (R) {
+            const bool nb = in && so > g.q0 - g.sh;
+            W[u][0] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(nb ? (uint32_t)so + 12u : kBufDrop), 0, 0);
+        } else {
+            const bool nb = in && so + 16 - g.sh < g.q1;
+            W[u][4] = __builtin_amdgcn_raw_buffer_load_b32(r, (int)(nb ? (uint32_t)so + 32u : kBufDrop), 0, 0);
         }
     }
 }
 
 template <int U, bool R>
 __device__ __forceinline__ void sseg_store(const SSeg& g, int fb, int lane, const uint32_t (&W)[U][5]) {
+    const __amdgpu_buffer_rsrc_t r = sseg_rsrc(g);
     const int a = R ? 4 - g.sh : g.sh;  // byte offset of the output inside the 20 bytes
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int f = fb + u * 64 + lane;
-        if (f >= g.n) continue;
         const int so = (R ? g.n - 1 - f : f) << 4;
         uint32_t o[4];
         if (a == 4) {
@@ -151,7 +161,8 @@ __device__ __forceinline__ void sseg_store(const SSeg& g, int fb, int lane, cons
                 o[i] = (o[i] & bm) | (cur & ~bm);
             }
         }
-        *gp(reinterpret_cast<u32x4*>(g.base + so)) = u32x4{o[0], o[1], o[2], o[3]};
+        const v4u ov = {o[0], o[1], o[2], o[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(ov, r, (int)(f < g.n ? (uint32_t)so + 16u : kBufDrop), 0, 0);
     }
 }
 

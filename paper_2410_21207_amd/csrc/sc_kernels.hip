@@ -712,9 +712,10 @@ struct Carver {
             if (threadIdx.x == 0) {
                 sm.jend[P - 1] = jstar;
                 __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, (uint32_t)P * (uint32_t)d.W);
                 int j = jstar;
                 for (int p = P - 1; p >= 1; --p) {
-                    j = min(max(j + (int)ld<TEAM>(d.anc + (size_t)p * d.W + j), 0), w - 1);
+                    j = min(max(j + (int)(int8_t)buf_ld8<TEAM>(ranc, (uint32_t)p * (uint32_t)d.W + (uint32_t)j), 0), w - 1);
                     sm.jend[p - 1] = j;
                     __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -722,6 +723,7 @@ struct Carver {
             // Each wave owns an equal range of rows [ra, rb) for the walk's output, the removal and
             // the band update.  It walks every phase its range touches (bottom phase first: phase
             // ends become known from the bottom up) and keeps the rows of its range.
+            const __amdgpu_buffer_rsrc_t rdw = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * (uint32_t)d.db * 4u);
             for (int p = (rb - 1) / KR; ra < rb && p >= ra / KR; --p) {
                 const int r0 = p * KR, r1 = min(H, r0 + KR), n = r1 - r0;
                 const int ia = max(ra, r0) - r0, ib = min(rb, r1) - r0;  // this wave's rows of the phase
@@ -734,20 +736,24 @@ struct Carver {
                 const int cb0 = max(0, je - KR) >> 2;
                 uint32_t* win = sm.win[wv];
                 {
-                    // all of a lane's loads are issued before its LDS writes (one memory round trip)
-                    constexpr int NI = (KR / 4 * GW + 63) / 64;
-                    const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs) + (size_t)(r0 >> 2) * d.db;
-                    const int g0 = ia >> 2, nx = (((n + 3) >> 2) - g0) * GW;  // groups holding rows ia .. n-1
-                    uint32_t v[NI];
+                    // lane q < GW loads byte-dword cb0 + q of every 4-row group the walk reads
+                    // (groups ia/4 .. of the phase): one buffer load per group at the same per-lane
+                    // offset and a scalar group offset, all issued before the LDS writes (one
+                    // memory round trip); lanes past the window or the map load nothing
+                    constexpr int GK = KR / 4;
+                    const int g0 = ia >> 2, ng = (n + 3) >> 2;  // groups holding rows ia .. n-1
+                    const uint32_t lo = lane < GW && cb0 + lane < d.db ? (uint32_t)(cb0 + lane) * 4u : kBufDrop;
+                    const uint32_t gb = (uint32_t)d.db * 4u;
+                    uint32_t v[GK];
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        const int x = lane + 64 * j, g = g0 + x / GW, q = x % GW;
-                        v[j] = x < nx && cb0 + q < d.db ? ld<TEAM>(src + (size_t)g * d.db + cb0 + q) : 0u;
-                    }
+                    for (int j = 0; j < GK; ++j)
+                        v[j] = j >= g0 && j < ng ? __builtin_amdgcn_raw_buffer_load_b32(
+                                                       rdw, (int)lo, (int)((uint32_t)((r0 >> 2) + j) * gb), TEAM ? 16 : 0)
+                                                 : 0u;
+                    if (lane < GW) {
 #pragma unroll
-                    for (int j = 0; j < NI; ++j) {
-                        const int x = lane + 64 * j;
-                        if (x < nx) win[(g0 + x / GW) * GW + x % GW] = v[j];
+                        for (int j = 0; j < GK; ++j)
+                            if (j >= g0 && j < ng) win[j * GW + lane] = v[j];
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -809,11 +815,11 @@ struct Carver {
                             b1 = a1; b1.n = 0;
                         }
                         if (ra) {
-                            if (rb) shift_rows2_wave<2, true, true>(a0, a1, b0, b1, lane);
-                            else shift_rows2_wave<2, true, false>(a0, a1, b0, b1, lane);
+                            if (rb) shift_rows2_wave<1, true, true>(a0, a1, b0, b1, lane);
+                            else shift_rows2_wave<1, true, false>(a0, a1, b0, b1, lane);
                         } else {
-                            if (rb) shift_rows2_wave<2, false, true>(a0, a1, b0, b1, lane);
-                            else shift_rows2_wave<2, false, false>(a0, a1, b0, b1, lane);
+                            if (rb) shift_rows2_wave<1, false, true>(a0, a1, b0, b1, lane);
+                            else shift_rows2_wave<1, false, false>(a0, a1, b0, b1, lane);
                         }
                     }
                 }

@@ -333,7 +333,7 @@ struct Carver : PixRow<C, CPL> {
                 SSeg a0, a1, b0, b1;
                 segs(0, a0, a1);
                 segs(1, b0, b1);
-                shift_rows2_wave<2, false, false>(a0, a1, b0, b1, lane);
+                shift_rows2_wave<1, false, false>(a0, a1, b0, b1, lane);
             }
             __syncthreads();
             if (t == 0) {  // device clock per stage: DP sweep; argmin + backtrack; removal
