@@ -133,7 +133,7 @@ struct Carver {
             ring[u] = __builtin_amdgcn_raw_buffer_load_b128(rwk, (int)v0, (int)((uint32_t)min(u, H - 1) * (uint32_t)d.wp),
                                                             kSc1);
         });
-        uint32_t Sk[CPL], Pup[CPL], dacc = 0;
+        uint32_t Sk[CPL], Pup[CPL], dacc = 0, dkeep = 0;
         int phase = 0;
 
         // end of a phase: the owned columns' ancestor offsets, then (every XP phases, not after the
@@ -157,11 +157,13 @@ struct Carver {
                 asm volatile("" ::: "memory");
                 if (mghost) {
                     unsigned long long t0 = 0;
+                    // plain buffer loads with the sc1 bit (an atomic load would make the compiler
+                    // wait for every access in flight at later loads)
+                    const __amdgpu_buffer_rsrc_t rxq = make_rsrc(xq, (uint32_t)(2 * d.xw) * 4u);
+                    const uint32_t xo = (uint32_t)(xr - xq) * 4u;
                     for (int it = 0;; ++it) {
-                        const uint64_t x01 = ld<true>(reinterpret_cast<const uint64_t*>(xr));
-                        const uint64_t x23 = ld<true>(reinterpret_cast<const uint64_t*>(xr) + 1);
-                        const uint32_t x[CPL] = {(uint32_t)x01, (uint32_t)(x01 >> 32), (uint32_t)x23,
-                                                 (uint32_t)(x23 >> 32)};
+                        const v4u xv = __builtin_amdgcn_raw_buffer_load_b128(rxq, (int)xo, 0, kSc1);
+                        const uint32_t x[CPL] = {xv[0], xv[1], xv[2], xv[3]};
                         bool ok = true;
 #pragma unroll
                         for (int c = 0; c < CPL; ++c) ok = ok && (!act[c] || (x[c] & 0x1FFu) == tag);
@@ -216,9 +218,11 @@ struct Carver {
             constexpr int u = decltype(U)::value;
             constexpr bool last = decltype(LAST)::value;  // the block holds row H-1: no refill
             const v4u px = ring[u];
-            if (!last)
+            if (!last) {
                 ring[u] = __builtin_amdgcn_raw_buffer_load_b128(rwk, (int)v0,
                                                                 (int)((uint32_t)min(i + PF, H - 1) * (uint32_t)d.wp), kSc1);
+                __builtin_amdgcn_sched_barrier(0);  // keep the refill PF rows ahead of its use
+            }
             // pixels j0-1 .. j0+4: the neighbours come from the lanes beside (the left one clamped
             // to column 0 at the image's left edge, the right one to the pixel itself past the row)
             uint32_t pc[CPL + 2];
@@ -264,7 +268,18 @@ struct Carver {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) Pup[c] = pc[c + 1];
             dacc |= (bits & 0xFFu) << (8 * (u & 3));
-            if ((u & 3) == 3 || (last && i == H - 1)) {
+            if constexpr (!last) {
+                // a full block stores its two groups together at its end (a store between the
+                // pixel prefetches would make the next row's wait cover the loads issued after it)
+                if constexpr (u == 3) {
+                    dkeep = dacc;
+                    dacc = 0;
+                } else if constexpr (u == PF - 1) {
+                    __builtin_amdgcn_raw_buffer_store_b32(dkeep, rdir, (int)dvo, (int)((uint32_t)((i - 4) >> 2) * gbytes), 0);
+                    __builtin_amdgcn_raw_buffer_store_b32(dacc, rdir, (int)dvo, (int)((uint32_t)(i >> 2) * gbytes), 0);
+                    dacc = 0;
+                }
+            } else if ((u & 3) == 3 || i == H - 1) {
                 __builtin_amdgcn_raw_buffer_store_b32(dacc, rdir, (int)dvo, (int)((uint32_t)(i >> 2) * gbytes), 0);
                 dacc = 0;
             }
@@ -361,8 +376,9 @@ struct Carver {
                 int je = min(max((int)(key & 0xFFFFFFFFu), 0), w - 1);
                 sm.jend[P - 1] = je;
                 __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, (uint32_t)P * (uint32_t)d.W);
                 for (int p = P - 1; p > 0; --p) {
-                    const int a = (int)ld<true>(reinterpret_cast<const uint8_t*>(d.anc) + (size_t)p * d.W + je);
+                    const int a = (int)buf_ld8<true>(ranc, (uint32_t)p * (uint32_t)d.W + (uint32_t)je);
                     je = min(max(je + a - 64, 0), w - 1);
                     sm.jend[p - 1] = je;
                     __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -371,6 +387,7 @@ struct Carver {
             // ---- the rows of this member's phases (p = rank, rank + G, ...): one wave per phase
             // walks it from an LDS window of the direction map, then removes its rows
             const int np = P > rank + G * wv ? (P - 1 - rank - G * wv) / (G * NW) + 1 : 0;  // phases of this wave
+            const __amdgpu_buffer_rsrc_t rdw = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * (uint32_t)d.db * 4u);
 #pragma unroll 1
             for (int q = np - 1; q >= 0; --q) {
                 const int p = rank + G * wv + G * NW * q;
@@ -382,11 +399,15 @@ struct Carver {
                 uint32_t* win = sm.win[wv];
                 constexpr int NI = (GK * WD + 63) / 64;
                 uint32_t v[NI];
-                const uint32_t* src = reinterpret_cast<const uint32_t*>(d.dirs) + (size_t)(r0 >> 2) * d.db;
+                // buffer loads with the sc1 bit at 32-bit offsets, dropped outside the map: no
+                // branches, so all of them go out before the first wait
 #pragma unroll
                 for (int mi = 0; mi < NI; ++mi) {
                     const int x = lane + 64 * mi, g = x / WD, qd = x % WD;
-                    v[mi] = g < ng && cb0 + qd < d.db ? ld<true>(src + (size_t)g * d.db + cb0 + qd) : 0u;
+                    const uint32_t off = g < ng && cb0 + qd < d.db
+                                             ? ((uint32_t)((r0 >> 2) + g) * (uint32_t)d.db + (uint32_t)(cb0 + qd)) * 4u
+                                             : kBufDrop;
+                    v[mi] = buf_ld32<true>(rdw, off);
                 }
 #pragma unroll
                 for (int mi = 0; mi < NI; ++mi) {

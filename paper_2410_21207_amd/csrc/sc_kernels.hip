@@ -66,17 +66,25 @@ __device__ __forceinline__ uint32_t energy_at(const uint8_t* img, long long pitc
     return s;
 }
 
-// e1 energy at logical column x of a row whose pixel 0 is at `r`, with the rows above and below
-// given the same way (min-side removal keeps every row at its own offset).
+// e1 energy at logical column x of a row from a buffer: the row starts at byte offset br of the
+// descriptor's memory, the rows above and below at bu and bd (min-side removal keeps every row at
+// its own offset).  The channel loop runs to 4 with dropped offsets past C, so the loads carry no
+// branches and go out together; a column outside [0, w) is clamped like the pixels of any other
+// (callers do not store its value).
 template <bool COH>
-__device__ __forceinline__ uint32_t energy_rows(const uint8_t* r, const uint8_t* ru, const uint8_t* rd, int w, int C,
-                                                int x) {
+__device__ __forceinline__ uint32_t energy_buf(__amdgpu_buffer_rsrc_t rb, uint32_t br, uint32_t bu, uint32_t bd, int w,
+                                               int C, int x) {
+    x = min(max(x, 0), w - 1);
     const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < w ? x + 1 : w - 1;
     uint32_t s = 0;
-    for (int c = 0; c < C; ++c) {
-        const int dx = (int)ld<COH>(r + xr * C + c) - (int)ld<COH>(r + xl * C + c);
-        const int dy = (int)ld<COH>(rd + x * C + c) - (int)ld<COH>(ru + x * C + c);
-        s += (uint32_t)(dx < 0 ? -dx : dx) + (uint32_t)(dy < 0 ? -dy : dy);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool ok = c < C;
+        const int a = (int)buf_ld8<COH>(rb, ok ? br + (uint32_t)(xr * C + c) : kBufDrop);
+        const int b = (int)buf_ld8<COH>(rb, ok ? br + (uint32_t)(xl * C + c) : kBufDrop);
+        const int dn = (int)buf_ld8<COH>(rb, ok ? bd + (uint32_t)(x * C + c) : kBufDrop);
+        const int up = (int)buf_ld8<COH>(rb, ok ? bu + (uint32_t)(x * C + c) : kBufDrop);
+        s += (uint32_t)abs(a - b) + (uint32_t)abs(dn - up);
     }
     return s;
 }
@@ -829,20 +837,27 @@ struct Carver {
             if (d.mode) break;
             if (rank == 0 && threadIdx.x == 0)
                 __hip_atomic_store(gp(d.amin), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // ---- band energy (a2): only the new columns s-1 and s of each row changed
+            // ---- band energy (a2): only the new columns s-1 and s of each row changed.  Buffer
+            // loads (sc1 in a team: the rows above and below were shifted by other workgroups) at
+            // 32-bit offsets; a lane past the wave's rows reads row ra and stores nothing.
             const int w2 = w - 1;
+            const __amdgpu_buffer_rsrc_t rwk = make_rsrc(d.wk, (uint32_t)H * (uint32_t)d.wp);
+            const __amdgpu_buffer_rsrc_t rsm = make_rsrc(d.seam, (uint32_t)H * 4u);
+            const __amdgpu_buffer_rsrc_t rof = make_rsrc(d.ro, (uint32_t)H * 4u);
             for (int rc = ra; rc < rb; rc += 64) {
-                const int r = rc + lane;
-                if (r < rb) {
-                    const int s = min(max(ld<TEAM>(d.seam + r), 0), w - 1);
-                    const int ru = r > 0 ? r - 1 : 0, rd = r + 1 < H ? r + 1 : H - 1;
-                    const int o = ld<TEAM>(d.ro + r);
-                    const uint8_t* pr = d.wk + (long long)r * d.wp + (long long)o * d.C;
-                    const uint8_t* pu = d.wk + (long long)ru * d.wp + (long long)ld<TEAM>(d.ro + ru) * d.C;
-                    const uint8_t* pd = d.wk + (long long)rd * d.wp + (long long)ld<TEAM>(d.ro + rd) * d.C;
+                const int r = rc + lane < rb ? rc + lane : ra;
+                const int ru = r > 0 ? r - 1 : 0, rd = r + 1 < H ? r + 1 : H - 1;
+                const int s = min(max((int)buf_ld32<TEAM>(rsm, (uint32_t)r * 4u), 0), w - 1);
+                const int o = (int)buf_ld32<TEAM>(rof, (uint32_t)r * 4u);
+                const uint32_t br = (uint32_t)r * (uint32_t)d.wp + (uint32_t)(o * d.C);
+                const uint32_t bu = (uint32_t)ru * (uint32_t)d.wp + buf_ld32<TEAM>(rof, (uint32_t)ru * 4u) * (uint32_t)d.C;
+                const uint32_t bd = (uint32_t)rd * (uint32_t)d.wp + buf_ld32<TEAM>(rof, (uint32_t)rd * 4u) * (uint32_t)d.C;
+                const uint32_t e0 = energy_buf<TEAM>(rwk, br, bu, bd, w2, d.C, s - 1);
+                const uint32_t e1 = energy_buf<TEAM>(rwk, br, bu, bd, w2, d.C, s);
+                if (rc + lane < rb) {
                     uint16_t* er = d.e + (size_t)r * d.ep + o;
-                    if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s - 1);
-                    if (s < w2) *gp(er + s) = (uint16_t)energy_rows<TEAM>(pr, pu, pd, w2, d.C, s);
+                    if (s - 1 >= 0 && s - 1 < w2) *gp(er + s - 1) = (uint16_t)e0;
+                    if (s < w2) *gp(er + s) = (uint16_t)e1;
                 }
             }
             // a team's time budget: its first member decides before the seam's last barrier, every
