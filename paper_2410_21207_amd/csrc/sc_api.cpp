@@ -760,11 +760,11 @@ sc_status check_fwd_image(int H, int W, int C, int pitch) {
 }
 
 // DP members of a forward team (the members whose windows cover the columns) and the team size
-// that also gives every wave of the team at most one phase of rows to walk and remove.
+// whose waves (four per member) each walk and remove at most half a phase of rows.
 int fwd_dp_members(int W) { return W <= sc::kFwtSingle ? 1 : (W + sc::kFwtOwned - 1) / sc::kFwtOwned; }
 int fwd_team_target(int H, int W) {
     const int P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
-    return std::min(32, std::max(fwd_dp_members(W), (P + 3) / 4));
+    return std::min(32, std::max(fwd_dp_members(W), (P + 1) / 2));
 }
 
 sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,

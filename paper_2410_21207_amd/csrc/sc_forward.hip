@@ -25,9 +25,9 @@
 // exchange rows (by phase parity) neither can then overwrite a row the other still has to read.
 //
 // Per seam: the DP and the argmin of the owned last-row columns (atomic minimum), a team barrier,
-// then every member hops through the phase ancestors itself, walks the rows of its own phases
-// (phase p belongs to member p mod G) from LDS windows of the 2-bit direction map and removes
-// those rows (pixels right of the seam one column left), and a second team barrier.  Teams sit on
+// then every member hops through the phase ancestors itself, each wave of the team walks the
+// phases its equal share of the rows touches from LDS windows of the 2-bit direction map and
+// removes its rows (pixels right of the seam one column left), and a second team barrier.  Teams sit on
 // one XCD (checked at start; a misplaced team flags the image).
 #include "sc_device.h"
 
@@ -384,27 +384,30 @@ struct Carver {
                     __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
-            // ---- the rows of this member's phases (p = rank, rank + G, ...): one wave per phase
-            // walks it from an LDS window of the direction map, then removes its rows
-            const int np = P > rank + G * wv ? (P - 1 - rank - G * wv) / (G * NW) + 1 : 0;  // phases of this wave
+            // ---- every wave of the team owns an equal range of rows [ra, rb) (waves numbered across
+            // the team first); it walks each phase its range touches from an LDS window of the
+            // direction map, bottom phase first as phase ends become known, and removes its rows
+            const int TW = G * NW, tw = wv * G + rank;
+            const int rpw = (H + TW - 1) / TW;
+            const int ra = min(H, tw * rpw), rb = min(H, ra + rpw);
             const __amdgpu_buffer_rsrc_t rdw = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * (uint32_t)d.db * 4u);
 #pragma unroll 1
-            for (int q = np - 1; q >= 0; --q) {
-                const int p = rank + G * wv + G * NW * q;
+            for (int p = (rb - 1) / K; ra < rb && p >= ra / K; --p) {
                 while (__hip_atomic_load(&sm.chain, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > p)
                     __builtin_amdgcn_s_sleep(1);
                 const int r0 = p * K, n = min(K, H - r0), ng = (n + 3) >> 2;
+                const int ia = max(ra, r0) - r0, ib = min(rb, r0 + n) - r0;  // this wave's rows of the phase
                 const int je = sm.jend[p];
                 const int cb0 = max(0, je - (K - 1)) >> 2;
                 uint32_t* win = sm.win[wv];
                 constexpr int NI = (GK * WD + 63) / 64;
                 uint32_t v[NI];
-                // buffer loads with the sc1 bit at 32-bit offsets, dropped outside the map: no
-                // branches, so all of them go out before the first wait
+                // buffer loads with the sc1 bit at 32-bit offsets, dropped outside the map and above
+                // the wave's first group: no branches, so all of them go out before the first wait
 #pragma unroll
                 for (int mi = 0; mi < NI; ++mi) {
                     const int x = lane + 64 * mi, g = x / WD, qd = x % WD;
-                    const uint32_t off = g < ng && cb0 + qd < d.db
+                    const uint32_t off = g >= (ia >> 2) && g < ng && cb0 + qd < d.db
                                              ? ((uint32_t)((r0 >> 2) + g) * (uint32_t)d.db + (uint32_t)(cb0 + qd)) * 4u
                                              : kBufDrop;
                     v[mi] = buf_ld32<true>(rdw, off);
@@ -418,7 +421,7 @@ struct Carver {
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 int s = je, mys = 0;
-                for (int i = n - 1; i >= 0; --i) {
+                for (int i = n - 1; i >= ia; --i) {
                     if (lane == i) mys = s;
                     if (i > 0) {
                         const int qd = min(max((s >> 2) - cb0, 0), WD - 1);
@@ -427,17 +430,17 @@ struct Carver {
                         s = min(max(s, 0), w - 1);
                     }
                 }
-                if (lane < n && d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
+                if (lane >= ia && lane < ib && d.seams_out) *gp(d.seams_out + (size_t)k * H + r0 + lane) = mys;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 // removal: in each row the pixels right of the seam move one column left, four
                 // rows per memory round trip
 #pragma unroll 1
-                for (int i = 0; i < n; i += 4) {
+                for (int i = ia; i < ib; i += 4) {
                     auto seg = [&](int q) {
                         SSeg g;
-                        if (i + q >= n) {
+                        if (i + q >= ib) {
                             g.base = d.wk;
                             g.q0 = g.q1 = g.sh = g.n = 0;
                             return g;
