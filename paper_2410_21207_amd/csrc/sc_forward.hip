@@ -56,6 +56,7 @@ struct Smem {
     uint32_t win[NW][GK * WD];
     int jend[PMAX];
     unsigned long long red[NW];
+    uint32_t cw[(252 / K + 1) * 128];  // the backtrack's windows of ancestor offsets, 512 bytes per phase
     int flag;
     int chain;  // jend[p] is final for every p >= chain
 };
@@ -368,20 +369,58 @@ struct Carver {
                 // reset before any member's minimum of seam k + 1
                 __hip_atomic_store(gp(d.amk + ((k + 1) & 1)), ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // ---- backtrack, first hop (every member on its own): thread 0 goes phase by phase
+            // ---- backtrack, first hop (every member on its own): wave 0 goes phase by phase
             // through the ancestor offsets and publishes each phase end in LDS as soon as it is
             // known; a wave starts on one of its phases once that phase's end is there, bottom
             // phases first.  (sm.chain was set above every phase before the DP's barriers.)
-            if (t == 0) {
+            // A phase end lies within K columns of the one below it, so wave 0 loads the ancestor
+            // offsets of CH phases at once (the 512 bytes of each row around the current column,
+            // two dwords per lane, into LDS) and lane 0 takes CH hops from there: one memory round
+            // trip per CH hops instead of one per hop.
+            if (wv == 0) {
+                constexpr int CH = 252 / K + 1;  // h * K + 3 < 256 for every hop h of a round
+                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, ((uint32_t)P * (uint32_t)d.W + 3u) & ~3u);
                 int je = min(max((int)(key & 0xFFFFFFFFu), 0), w - 1);
-                sm.jend[P - 1] = je;
-                __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, (uint32_t)P * (uint32_t)d.W);
-                for (int p = P - 1; p > 0; --p) {
-                    const int a = (int)buf_ld8<true>(ranc, (uint32_t)p * (uint32_t)d.W + (uint32_t)je);
-                    je = min(max(je + a - 64, 0), w - 1);
-                    sm.jend[p - 1] = je;
-                    __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (lane == 0) {
+                    sm.jend[P - 1] = je;
+                    __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                for (int p = P - 1; p >= 1; p -= CH) {
+                    const int m = min(CH, p);
+                    uint32_t v[CH][2];
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        // byte window [o, o + 512) of phase p - h's row, o = row + je - 256 rounded
+                        // down to a dword; dwords before the array are dropped
+                        const int o = (p - h) * d.W + je - 256;
+                        const int oa = o >= 0 ? o & ~3 : -((-o + 3) & ~3);
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const int bo = oa + 4 * (lane + 64 * q);
+                            v[h][q] = buf_ld32<true>(ranc, h < m && bo >= 0 ? (uint32_t)bo : kBufDrop);
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        sm.cw[h * 128 + lane] = v[h][0];
+                        sm.cw[h * 128 + 64 + lane] = v[h][1];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (lane == 0) {
+                        const uint8_t* cb = reinterpret_cast<const uint8_t*>(sm.cw);
+                        const int j0 = je;
+                        for (int h = 0; h < m; ++h) {
+                            const int o = (p - h) * d.W + j0 - 256;
+                            const int oa = o >= 0 ? o & ~3 : -((-o + 3) & ~3);
+                            je = min(max(je + (int)cb[h * 512 + (p - h) * d.W + je - oa] - 64, 0), w - 1);
+                            sm.jend[p - 1 - h] = je;
+                            __hip_atomic_store(&sm.chain, p - 1 - h, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                    je = __builtin_amdgcn_readfirstlane(je);  // lane 0's column, after its LDS reads
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
             // ---- every wave of the team owns an equal range of rows [ra, rb) (waves numbered across

@@ -714,18 +714,59 @@ struct Carver {
             const unsigned long long key = __hip_atomic_load(gp(d.amin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int jstar = min(max((int)(key & 0xffffffffu), 0), w - 1);
             if (rank == 0 && threadIdx.x == 0 && d.costs_out) *gp(d.costs_out + k) = (long long)(key >> 32);
-            // ---- backtrack (a5): thread 0 hops from phase end to phase end and publishes the seam
-            // column at every phase end as soon as it is known; the waves walk their phases' rows
-            // from LDS windows of the direction map as their phase ends become known.
-            if (threadIdx.x == 0) {
-                sm.jend[P - 1] = jstar;
-                __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, (uint32_t)P * (uint32_t)d.W);
+            // ---- backtrack (a5): wave 0 hops from phase end to phase end and publishes the seam
+            // column at every phase end in LDS as soon as it is known; the waves walk their phases'
+            // rows from LDS windows of the direction map as their phase ends become known.  A phase
+            // end lies within KR columns of the one below it, so a round loads the ancestor offsets
+            // of CH phases at once (the 512 bytes of each row around the current column, two dwords
+            // per lane, into LDS that the DP no longer uses) and lane 0 takes CH hops from there:
+            // one memory round trip per CH hops instead of one per hop.
+            if (wv == 0) {
+                constexpr int CH = 252 / KR + 1;  // h * KR + 3 < 256 for every hop h of a round
+                static_assert(CH * 128 <= 2 * kLdsExchangeMaxW, "hop windows fit the exchange rows");
+                uint32_t* cw = &sm.xs[0][0];
+                const __amdgpu_buffer_rsrc_t ranc = make_rsrc(d.anc, ((uint32_t)P * (uint32_t)d.W + 3u) & ~3u);
                 int j = jstar;
-                for (int p = P - 1; p >= 1; --p) {
-                    j = min(max(j + (int)(int8_t)buf_ld8<TEAM>(ranc, (uint32_t)p * (uint32_t)d.W + (uint32_t)j), 0), w - 1);
-                    sm.jend[p - 1] = j;
-                    __hip_atomic_store(&sm.chain, p - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (lane == 0) {
+                    sm.jend[P - 1] = j;
+                    __hip_atomic_store(&sm.chain, P - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                for (int p = P - 1; p >= 1; p -= CH) {
+                    const int m = min(CH, p);
+                    uint32_t v[CH][2];
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        // byte window [o, o + 512) of phase p - h's row, o = row + j - 256 rounded
+                        // down to a dword; dwords before the array are dropped
+                        const int o = (p - h) * d.W + j - 256;
+                        const int oa = o >= 0 ? o & ~3 : -((-o + 3) & ~3);
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const int bo = oa + 4 * (lane + 64 * q);
+                            v[h][q] = buf_ld32<TEAM>(ranc, h < m && bo >= 0 ? (uint32_t)bo : kBufDrop);
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < CH; ++h) {
+                        cw[h * 128 + lane] = v[h][0];
+                        cw[h * 128 + 64 + lane] = v[h][1];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (lane == 0) {
+                        const uint8_t* cb = reinterpret_cast<const uint8_t*>(cw);
+                        const int j0 = j;
+                        for (int h = 0; h < m; ++h) {
+                            const int o = (p - h) * d.W + j0 - 256;
+                            const int oa = o >= 0 ? o & ~3 : -((-o + 3) & ~3);
+                            j = min(max(j + (int)(int8_t)cb[h * 512 + (p - h) * d.W + j - oa], 0), w - 1);
+                            sm.jend[p - 1 - h] = j;
+                            __hip_atomic_store(&sm.chain, p - 1 - h, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                    j = __builtin_amdgcn_readfirstlane(j);  // lane 0's column, after its LDS reads
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
             // Each wave owns an equal range of rows [ra, rb) for the walk's output, the removal and
