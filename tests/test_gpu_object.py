@@ -1,8 +1,9 @@
 """GPU parity of object removal with a mask (sc_remove_object) against the oracle: the output
 image, the direction, the number of seams, the masked pixels left, every seam and every masked
 cost, bit-exact.  Sizes span several 60-row phases and thread column ranges with ragged tails,
-both directions, C = 1..4, masks with stray pixels, the restore rounds, the 8-column-per-thread
-path (frames wider than 4096) and phase ancestors spilled from LDS to the workspace."""
+both directions, C = 1..4, masks with stray pixels, the restore rounds, frames wider than half the
+workgroup's column range, the 8-column-per-thread path (frames wider than 4096) and phase
+ancestors spilled from LDS to the workspace."""
 import numpy as np
 import pytest
 import torch
@@ -80,8 +81,11 @@ def test_object_edge_cases():
 
 
 def test_object_wide_and_spilled_ancestors():
-    # a frame wider than 4096 columns (8 columns per thread) and one whose phase ancestors
-    # (phases x width bytes) exceed the LDS share and go to the workspace
+    # frames wider than 2048 and than 4096 columns (8 columns per thread), and one whose phase
+    # ancestors (phases x width bytes) exceed the LDS share and go to the workspace
+    img = synth.blob_image(64, 2600, 3, seed=10)
+    m = synth.ellipse_mask(64, 2600, 30, 2100, 28, 5)
+    _compare(img, m, direction=0, where="2600 wide")
     img = synth.blob_image(70, 4500, 3, seed=8)
     m = synth.ellipse_mask(70, 4500, 35, 3000, 30, 6)
     _compare(img, m, direction=0, where="4500 wide")
