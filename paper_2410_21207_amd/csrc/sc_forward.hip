@@ -125,8 +125,13 @@ struct Carver {
         uint32_t* const xq = d.xq;
         const bool noL = j0 == 0;  // column 0 has no upper-left parent
         bool okR[CPL];             // the column has an upper-right parent
+        uint32_t tagR[CPL];        // the upper-right candidate's tag, or all ones (INF) without that parent
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) okR[c] = j0 + c + 1 < w;
+        for (int c = 0; c < CPL; ++c) {
+            okR[c] = j0 + c + 1 < w;
+            tagR[c] = okR[c] ? 0x100u : INF;
+        }
+        const uint32_t infL = noL ? INF : 0u;  // column 0 has no upper-left parent
 
         v4u ring[PF];
         static_for<PF>([&](auto U) {
@@ -256,9 +261,9 @@ struct Carver {
                     const uint32_t sL = c == 0 ? Sl : Sk[c - 1];
                     const uint32_t sR = c == CPL - 1 ? Sr : Sk[c + 1];
                     uint32_t kL = (__builtin_amdgcn_sad_u8(Pup[c], pl, 0u) << 9) + sL;
-                    if (c == 0 && noL) kL = INF;
+                    if (c == 0) kL |= infL;
                     const uint32_t kU = Sk[c] | 0x80u;
-                    const uint32_t kR = okR[c] ? ((__builtin_amdgcn_sad_u8(Pup[c], pr[c], 0u) << 9) + sR) | 0x100u : INF;
+                    const uint32_t kR = ((__builtin_amdgcn_sad_u8(Pup[c], pr[c], 0u) << 9) + sR) | tagR[c];
                     const uint32_t kk = min3u(kL, kU, kR);
                     Sn[c] = next_state(kk, cu);
                     bits |= ((kk >> 7) & 3u) << (2 * c);
