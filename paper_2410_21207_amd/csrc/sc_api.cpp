@@ -732,7 +732,7 @@ FwdLayout fwd_layout(int H, int W, int C) {
     FwdLayout L;
     L.P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
     L.db = (int)sc::align_up((size_t)(W + 3) / 4, 16);  // direction bytes (4 columns each) per row
-    L.wp = (int)sc::align_up((size_t)W * 4, 64);         // one dword per pixel
+    L.wp = (int)sc::align_up((size_t)(W + 1) * 4, 64);   // one dword per pixel, and a copy of the last
     L.xw = (int)sc::align_up((size_t)W + 8, 64);
     size_t off = 0;
     L.dirs = off;
@@ -760,11 +760,12 @@ sc_status check_fwd_image(int H, int W, int C, int pitch) {
 }
 
 // DP members of a forward team (the members whose windows cover the columns) and the team size
-// whose waves (four per member) each walk and remove at most half a phase of rows.
+// whose waves (four per member) each walk and remove at most 4/rows_per_wave_phases phases of
+// rows (half a phase by default).
 int fwd_dp_members(int W) { return W <= sc::kFwtSingle ? 1 : (W + sc::kFwtOwned - 1) / sc::kFwtOwned; }
-int fwd_team_target(int H, int W) {
+int fwd_team_target(int H, int W, int rows_per_wave_phases = 2) {
     const int P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
-    return std::min(32, std::max(fwd_dp_members(W), (P + 1) / 2));
+    return std::min(32, std::max(fwd_dp_members(W), (P + rows_per_wave_phases - 1) / rows_per_wave_phases));
 }
 
 sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
@@ -889,10 +890,16 @@ extern "C" sc_status sc_forward_batch_prepare(const sc_job* jobs, int n, void* w
     if (used > cap)
         return fail(SC_EUNSUPPORTED, "%lld workgroups of forward teams exceed the %lld resident ones; split the batch",
                     used, cap);
-    for (int i : order) {
-        const int grow = std::min<long long>(fwd_team_target(jobs[i].H, jobs[i].W) - gsz[i], cap - used);
+    // grow the teams while room is left: the image with the most work first toward half a phase of
+    // rows per wave (it sets the batch time), then every image toward a phase per wave, then toward
+    // half a phase, longest first
+    auto grow_to = [&](int i, int per) {
+        const int grow = std::min<long long>(fwd_team_target(jobs[i].H, jobs[i].W, per) - gsz[i], cap - used);
         if (grow > 0) gsz[i] += grow, used += grow;
-    }
+    };
+    grow_to(order[0], 2);
+    for (int per : {4, 2})
+        for (int i : order) grow_to(i, per);
     // placement: longest first, each team on the XCD with the most free slots
     int slots[8] = {0};
     std::vector<int2> blk;

@@ -116,7 +116,8 @@ struct Carver {
         const bool exact = (lane >= XG / CPL && lane < 64 - XG / CPL) || (wv == 0 && cl.base == 0 && lane < XG / CPL);
         const bool owned = exact && j0 >= cl.own0 && j0 < cl.own1 && j0 < w;  // groups of 4 are owned whole
         const bool mghost = any && (j0 < cl.own0 || j0 >= cl.own1);         // refreshed from other members
-        const uint32_t v0 = any ? (uint32_t)j0 * 4u : kBufDrop;
+        // the lane whose first column is w loads too: column w keeps a copy of the row's last pixel
+        const uint32_t v0 = j0 >= 0 && j0 <= w ? (uint32_t)j0 * 4u : kBufDrop;
         const __amdgpu_buffer_rsrc_t rwk = make_rsrc(d.wk, (uint32_t)H * (uint32_t)d.wp + (uint32_t)kFwdSlack);
         const uint32_t gbytes = (uint32_t)d.db * 4u;
         const __amdgpu_buffer_rsrc_t rdir = make_rsrc(d.dirs, (uint32_t)((H + 3) >> 2) * gbytes);
@@ -241,9 +242,11 @@ struct Carver {
             const uint32_t lpx = from_left(pc[4]);
             pc[5] = from_right(pc[1]);
             pc[0] = noL ? pc[1] : lpx;
+            // right neighbours: column w holds a copy of the last pixel, so the clamp at the row's
+            // end needs no select
             uint32_t pr[CPL];
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) pr[c] = okR[c] ? pc[c + 2] : pc[c + 1];
+            for (int c = 0; c < CPL; ++c) pr[c] = pc[c + 2];
             uint32_t bits = 0;
             if (u == 0 && i == 0) {
 #pragma unroll
@@ -491,9 +494,21 @@ struct Carver {
                         }
                         const int si = min(max(__builtin_amdgcn_readlane(mys, i + q), 0), w - 1);
                         uint8_t* r = d.wk + (long long)(r0 + i + q) * d.wp;
-                        return sseg<false>(r + (long long)si * 4, r + (long long)(w - 1) * 4, 4);
+                        // columns si+1 .. w move left, the copy of the last pixel at w included,
+                        // so column w-1 then holds a copy of the new last pixel
+                        return sseg<false>(r + (long long)si * 4, r + (long long)w * 4, 4);
                     };
                     shift_rows2_wave<2, false, false>(seg(0), seg(1), seg(2), seg(3), lane);
+                    // a seam at the last column removed the pixel the copy repeated: the new last
+                    // pixel (w-2) is copied to w-1 (after the shift's store to it, same wave)
+                    const int sq = __shfl(mys, min(i + lane, 63), 64);  // row i + lane's seam, in lanes 0..3
+                    if (lane < 4 && i + lane < ib && w >= 2) {
+                        const int si = min(max(sq, 0), w - 1);
+                        if (si == w - 1) {
+                            uint32_t* r = reinterpret_cast<uint32_t*>(d.wk + (long long)(r0 + i + lane) * d.wp);
+                            *gp(r + w - 1) = *gp(r + w - 2);
+                        }
+                    }
                 }
             }
             if (G > 1) {
@@ -575,6 +590,12 @@ __device__ void fwt_prepare_rows(const Img& d, const uint8_t* srcimg, int row0, 
 #pragma unroll
                 for (int p = 0; p < 4; ++p)
                     if (x0 + p < W) *gp(wr + x0 + p) = r.px(p);
+            }
+            // column W keeps a copy of the last pixel (the DP's right neighbour at the row's end)
+            if (x0 + 4 >= W) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+                    if (x0 + p == W - 1) *gp(wr + W) = r.px(p);
             }
             if (identity) {
                 uint8_t* o = d.img + (long long)y * d.pitch + (long long)x0 * C;
