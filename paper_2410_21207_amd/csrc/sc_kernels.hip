@@ -399,22 +399,31 @@ struct Carver {
 
     // One DP row for the CPL columns of this lane.  Q holds the previous row's keys (the tag bits
     // [1:0] are ignored); on return Q holds this row's keys and the result's top 2*CPL bits hold
-    // this row's directions, column 0 lowest.
-    static __device__ __forceinline__ uint32_t row_step(uint32_t (&Q)[CPL], const EV& ev) {
+    // this row's directions, column 0 lowest.  EDGE: the window reaches past the image; a column
+    // outside [0, w) must never be a parent, so the candidates that cross the image's edges are
+    // made all ones by saturating adds of per-lane words (radd[j]: 10, or all ones when column j
+    // is outside; ladd: 0, or all ones when the lane's last column is outside).  The keys of the
+    // outside columns themselves are never read.
+    template <bool EDGE>
+    static __device__ __forceinline__ uint32_t row_step(uint32_t (&Q)[CPL], const EV& ev, const uint32_t (&radd)[CPL],
+                                                        uint32_t ladd) {
         uint32_t t[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) t[k] = Q[k] & ~3u;
         // The neighbours of the lane's first and last column live in lanes -1 and +1.  At the
         // wave's edges the shift fills in 0: those columns are halo, and within a phase a wrong
         // value there moves at most one column inward per row, never reaching an owned column.
-        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)t[CPL - 1], 0x138, 0xf, 0xf, true);
-        const uint32_t rightR = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(t[0] + 10u), 0x130, 0xf, 0xf, true);
+        const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(
+            0, (int)(EDGE ? __builtin_elementwise_add_sat(t[CPL - 1], ladd) : t[CPL - 1]), 0x138, 0xf, 0xf, true);
+        const uint32_t rightR = (uint32_t)__builtin_amdgcn_update_dpp(
+            0, (int)(EDGE ? __builtin_elementwise_add_sat(t[0], radd[0]) : t[0] + 10u), 0x130, 0xf, 0xf, true);
         uint32_t acc = 0;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             const uint32_t L = k ? t[k - 1] : left;                      // tag 0, offset +0
             const uint32_t Cc = t[k] + 5u;                               // tag 1, offset +1
-            const uint32_t R = k + 1 < CPL ? t[k + 1] + 10u : rightR;    // tag 2, offset +2
+            const uint32_t R = k + 1 < CPL ? (EDGE ? __builtin_elementwise_add_sat(t[k + 1], radd[k + 1]) : t[k + 1] + 10u)
+                                           : rightR;                     // tag 2, offset +2
             const uint32_t r = min(min(L, Cc), R);
             const uint32_t pair = (uint32_t)(ev.v[k >> 2] >> (((k >> 1) & 1) * 32));
             Q[k] = (k & 1) ? mad_hi16(pair, r) : mad_lo16(pair, r);
@@ -555,12 +564,14 @@ struct Carver {
                 __builtin_amdgcn_raw_buffer_store_b64(v, rdir, (int)doff, (int)((uint32_t)(r >> 2) * gbytes), 0);
             }
         };
-        auto step = [&](int r, const EV& ev) {
-            const uint32_t acc = row_step(Q, ev);
-            if (EDGE) {
+        // EDGE: the right candidate of a column next to the image's right end, and the left one
+        // of the image's column 0, saturate to all ones (the columns outside are never parents)
+        uint32_t radd[CPL];
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) Q[k] = valid[k] ? Q[k] : QINF;
-            }
+        for (int k = 0; k < CPL; ++k) radd[k] = valid[k] ? 10u : 0xFFFFFFFFu;
+        const uint32_t ladd = valid[CPL - 1] ? 0u : 0xFFFFFFFFu;
+        auto step = [&](int r, const EV& ev) {
+            const uint32_t acc = row_step<EDGE>(Q, ev, radd, ladd);
             // shift the group's bytes down one and put this row's byte on top: one v_perm_b32
             // (selector bytes 0-3 pick from pk, 4-7 from acc)
             if constexpr (CPL == 4) {
