@@ -424,8 +424,16 @@ sc_status sc_batch_prepare(const sc_job* jobs, int n, const sc_tune* tune, void*
     }
     blk.assign(nb_team, make_int2(-1, -1));
     for (auto& pr : placed) blk[pr.first] = pr.second;
-    for (int i : order) {
-        if (gsz[i] >= 2) continue;
+    // one workgroup per remaining image, in order of decreasing chain (seams x rows): a single
+    // workgroup's carve time follows its row chain more than its pixel work (a tall narrow image
+    // has little work but a long chain), and the longest must start first
+    std::vector<int> singles;
+    for (int i : order)
+        if (gsz[i] < 2) singles.push_back(i);
+    std::stable_sort(singles.begin(), singles.end(), [&](int a, int b) {
+        return (double)(jobs[a].W - jobs[a].target_w) * jobs[a].H > (double)(jobs[b].W - jobs[b].target_w) * jobs[b].H;
+    });
+    for (int i : singles) {
         const int t = (int)teams.size();
         teams.push_back(make_int2((int)team_imgs.size(), 1));
         team_imgs.push_back(i);
