@@ -68,7 +68,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // threads) for every compiled variant of the carve kernel; the launchers switch over the same list.
 #define SC_VARIANTS(X)                                                                                      \
     X(0, 4, 32, 256) X(1, 4, 32, 512) X(2, 4, 32, 1024) X(3, 8, 32, 512) X(4, 8, 32, 1024) X(5, 4, 48, 512) \
-    X(6, 4, 48, 256) X(7, 4, 56, 512) X(8, 4, 56, 256)
+    X(6, 4, 48, 256) X(7, 4, 56, 512) X(8, 4, 56, 256) X(9, 2, 48, 512)
 
 struct Variant {
     int cpl, kr, threads;
@@ -80,7 +80,6 @@ inline constexpr Variant kVariants[] = {SC_VARIANTS(SC_VARIANT_ROW)};
 inline int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 inline const Variant& variant(int v) { return kVariants[v]; }
 inline int default_variant() { return 7; }  // cpl4_k56_t512
-inline int team_variant() { return 7; }
 
 Layout layout_for(int H, int W, int C, int variant_kr_min);
 constexpr int kLdsExchangeMaxW = 4096;  // single-workgroup carves keep the phase exchange row in LDS up to this width

@@ -364,7 +364,7 @@ struct Carver {
     static constexpr int PF = 8;                         // rows of energy prefetched ahead
     static constexpr int WD = (KR / 2 + 2 + 3) / 4 + 1;  // dwords of a backtrack window row
     static constexpr int PMAX = 16448 / KR + 2;          // phases of the tallest image
-    static_assert(CPL == 4 || CPL == 8, "a lane's directions fill a byte or a short");
+    static_assert(CPL == 2 || CPL == 4 || CPL == 8, "a lane's directions fill half a byte, a byte or a short");
     static_assert(KR % CPL == 0 && KR % PF == 0 && KR <= 63 && S > 0 && S % 16 == 0, "phase shape");
 
     struct Smem {
@@ -377,7 +377,7 @@ struct Carver {
     };
 
     struct EV {
-        uint64_t v[CPL / 4];  // CPL uint16 energies
+        uint64_t v[(CPL + 3) / 4];  // CPL uint16 energies
     };
 
     // Energies at the lane's byte offset `off` (a valid column) of the row starting `soff` bytes
@@ -386,7 +386,9 @@ struct Carver {
     template <bool COH>
     static __device__ __forceinline__ EV load_ev(__amdgpu_buffer_rsrc_t re, uint32_t soff, uint32_t off) {
         EV e;
-        if constexpr (CPL == 4) {
+        if constexpr (CPL == 2) {
+            e.v[0] = __builtin_amdgcn_raw_buffer_load_b32(re, (int)off, (int)soff, COH ? 16 : 0);
+        } else if constexpr (CPL == 4) {
             const v2u v = __builtin_amdgcn_raw_buffer_load_b64(re, (int)off, (int)soff, COH ? 16 : 0);
             e.v[0] = ((uint64_t)v[1] << 32) | v[0];
         } else {
@@ -551,13 +553,21 @@ struct Carver {
         // direction byte b (4 columns, 2 bits each) of rows r & ~3 .. (r & ~3) + 3, lowest row in
         // the lowest byte.  A lane gathers its bytes of a group in registers and stores them once;
         // lanes that do not own their columns store to a dropped offset instead of branching.
-        const uint32_t doff = owned ? (uint32_t)(col0 >> 2) * 4u : kBufDrop;
+        const uint32_t doff = owned && (CPL != 2 || (lane & 1) == 0) ? (uint32_t)(col0 >> 2) * 4u : kBufDrop;
         const uint32_t gbytes = (uint32_t)d.db * 4u;  // bytes per 4-row group
         uint32_t pk0 = 0, pk1 = 0;                    // CPL 8: pk1 holds the lane's second byte
+        // CPL 2: a lane's two columns sit in the high half of each row byte; an even lane's byte
+        // takes them to the low half and its odd neighbour's (the next two columns) on top
+        auto pair_bytes = [](uint32_t pk) {
+            return (pk >> 4) | (uint32_t)__builtin_amdgcn_mov_dpp((int)pk, 0xF5, 0xf, 0xf, false);  // quad_perm 1,1,3,3
+        };
 
         auto flush = [&](int r) {  // r: the last row gathered; stores the group of row r
             const int sh = 8 * (3 - (r & 3));          // a partial group sits in the top bytes
-            if constexpr (CPL == 4) {
+            if constexpr (CPL == 2) {
+                __builtin_amdgcn_raw_buffer_store_b32(pair_bytes(pk0 >> sh), rdir, (int)doff,
+                                                      (int)((uint32_t)(r >> 2) * gbytes), 0);
+            } else if constexpr (CPL == 4) {
                 __builtin_amdgcn_raw_buffer_store_b32(pk0 >> sh, rdir, (int)doff, (int)((uint32_t)(r >> 2) * gbytes), 0);
             } else {
                 const v2u v = {pk0 >> sh, pk1 >> sh};
@@ -574,7 +584,7 @@ struct Carver {
             const uint32_t acc = row_step<EDGE>(Q, ev, radd, ladd);
             // shift the group's bytes down one and put this row's byte on top: one v_perm_b32
             // (selector bytes 0-3 pick from pk, 4-7 from acc)
-            if constexpr (CPL == 4) {
+            if constexpr (CPL <= 4) {
                 pk0 = __builtin_amdgcn_perm(acc, pk0, 0x07030201u);
             } else {
                 pk0 = __builtin_amdgcn_perm(acc, pk0, 0x06030201u);
@@ -588,7 +598,10 @@ struct Carver {
         uint32_t gk0 = 0, gk1 = 0;  // the block's first group
         auto flush_block = [&](int rb) {
             const uint32_t g0 = (uint32_t)(rb >> 2) * gbytes;
-            if constexpr (CPL == 4) {
+            if constexpr (CPL == 2) {
+                __builtin_amdgcn_raw_buffer_store_b32(pair_bytes(gk0), rdir, (int)doff, (int)g0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(pair_bytes(pk0), rdir, (int)doff, (int)(g0 + gbytes), 0);
+            } else if constexpr (CPL == 4) {
                 __builtin_amdgcn_raw_buffer_store_b32(gk0, rdir, (int)doff, (int)g0, 0);
                 __builtin_amdgcn_raw_buffer_store_b32(pk0, rdir, (int)doff, (int)(g0 + gbytes), 0);
             } else {

@@ -20,9 +20,11 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 
-# (variant id, largest team) pairs tried by default; variant ids index sc_variant_name()
+# (variant id, largest team) pairs tried by default; variant ids index sc_variant_name().  A batch
+# carves most of its images with one workgroup each, which the 2-columns-per-lane variant (9)
+# slows down, so only single images try it.
 BATCH_CANDIDATES = [(v, g) for v in (1, 5, 7) for g in (8, 16, 32)]
-SINGLE_CANDIDATES = [(v, g) for v in (1, 5, 7) for g in (4, 8, 16, 32)]
+SINGLE_CANDIDATES = [(v, g) for v in (1, 5, 7, 9) for g in (4, 8, 16, 32)]
 
 _cache: dict | None = None
 _cache_path: str | None = None

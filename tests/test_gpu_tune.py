@@ -22,7 +22,7 @@ def test_autotune_batch_candidates_agree(tmp_path, monkeypatch):
         jobs.append((synth.blob_image(H, W, 3, seed=500 + i), max(1, W - int(rng.integers(1, W // 3 + 2)))))
     srcs = [dev(img) for img, _ in jobs]
     imgs = [torch.empty_like(s) for s in srcs]
-    cands = [(1, 1), (7, 2), (5, 4)]
+    cands = [(1, 1), (7, 2), (5, 4), (9, 4)]
     log("autotune batch", cands)
     best, timings = tune.autotune_batch(imgs, [tw for _, tw in jobs], srcs=srcs, candidates=cands, reps=1, path=path)
     assert best in cands and set(timings) == set(cands)
