@@ -13,7 +13,8 @@
 //    wave shifts.  The three parent candidates get tags 0/1/2 (left, up,
 //    right) so one v_min3 picks the minimum AND the leftmost tie (reading R5),
 //    and the same add moves the ancestor offset.  The direction bits are
-//    shifted into a byte per lane with v_alignbit and stored as a 2-bit map.
+//    shifted into a byte per lane with v_alignbit (half a byte with CPL 2,
+//    which a lane pair joins) and stored as a 2-bit map.
 //  * A wave owns a strip of S = 64*CPL - 2*KR columns and computes KR halo
 //    columns on each side, so it runs KR rows with no exchange at all
 //    ("ghost zone" tiling); waves exchange the last row of every KR-row phase
@@ -22,8 +23,9 @@
 //    minimal path moved within the phase; the backtrack then hops phase by
 //    phase (one load per phase) and walks the KR rows of every phase in
 //    parallel from an LDS window of the direction map.
-//  * Removal shifts the bytes right of the seam one pixel left, row-parallel
-//    with coalesced 16-byte slots, for the image and the energy plane alike;
+//  * Removal shifts the shorter side of each row one pixel toward the seam
+//    (the right side only when min-side removal is off), row-parallel with
+//    coalesced 16-byte slots, for the image and the energy plane alike;
 //    the energy is then recomputed only at the two new columns {s-1, s} of
 //    each row (the only cells whose stencil changed).
 #include <mutex>
