@@ -113,6 +113,18 @@ def test_carve_variants_and_teams(variant, team):
     _carve_and_compare(img, 440, variant=variant, team=team)
 
 
+@pytest.mark.parametrize("H,W,C,tw,alpha,team", [(50, 301, 3, 240, 2, 1), (97, 211, 1, 150, 3, 2), (33, 450, 4, 400, 256, 3),
+                                                 (1, 50, 3, 10, 256, 1), (40, 2, 3, 1, 256, 1), (65, 193, 3, 1, 4, 4),
+                                                 (120, 1030, 3, 900, 3, 8)])
+def test_carve_two_columns_per_lane(H, W, C, tw, alpha, team):
+    """The variant whose lanes own two columns (their direction bits share a byte with the next
+    lane's): tie-heavy and ragged images, widths that end inside a lane pair and inside a strip,
+    single workgroups and teams; seams, costs and pixels equal to the oracle's."""
+    v = api.variants().index("cpl2_k48_t512")
+    log("carve cpl2", H, W, C, tw, alpha, team)
+    _carve_and_compare(rng_img(H * W + alpha + 7, H, W, C, alpha), tw, variant=v, team=team)
+
+
 @pytest.mark.parametrize("H,W,C,tw,alpha", [(50, 300, 3, 250, 2), (97, 211, 1, 150, 3), (33, 450, 4, 400, 256),
                                             (1, 50, 3, 10, 256), (40, 2, 3, 1, 256), (65, 193, 3, 1, 4)])
 def test_carve_tie_heavy_and_edges(H, W, C, tw, alpha):
