@@ -262,8 +262,10 @@ sc_status sc_carve_batch(const sc_job* jobs, int n, const sc_tune* tune, void* w
  * the pixel that becomes the border).  Ties, backtrack, removal and the seam
  * loop are those of sc_carve; the costs are recomputed from the current pixels
  * for every seam.  A team of 256-thread workgroups on one XCD carves one
- * image: each computes 976 columns (exact ones owned, 56 on each side shared
- * with the neighbours at every 56-row phase end).
+ * image: each DP member computes 976 columns and owns the middle 752; every
+ * second 56-row phase the members exchange the keys of the 112 columns on
+ * each side.  sc_carve_forward sizes the team so that every wave walks and
+ * removes about 8 rows of a seam (at most 32 workgroups).
  *
  * sc_carve_forward: arguments as sc_carve (no tune); seams_out/costs_out
  *   (nullable) receive every seam and its forward cost.  ws: at least

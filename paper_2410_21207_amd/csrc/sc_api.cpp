@@ -775,6 +775,9 @@ int fwd_team_target(int H, int W, int rows_per_wave_phases = 2) {
     const int P = (H + sc::kFwtPhaseRows - 1) / sc::kFwtPhaseRows;
     return std::min(32, std::max(fwd_dp_members(W), (P + rows_per_wave_phases - 1) / rows_per_wave_phases));
 }
+// A single image has the device to itself: its team grows until every wave walks and removes
+// about 8 rows (measured at 1920x1080: 97 ms with 32 workgroups, 99 ms with 20, 109 ms with 10).
+int fwd_single_team(int H, int W) { return std::min(32, std::max(fwd_dp_members(W), (H + 31) / 32)); }
 
 sc::Img make_fwd_img(const uint8_t* src, uint8_t* img, int H, int W, int C, long long pitch, int target_w,
                      int32_t* seams_out, int64_t* costs_out, char* base, sc::Ctl* ctl, int G) {
@@ -830,7 +833,7 @@ extern "C" sc_status sc_carve_forward(uint8_t* img, int H, int W, int C, int tar
     char* base = static_cast<char*>(ws);
     sc::Ctl* ctl = reinterpret_cast<sc::Ctl*>(base + sizeof(WsHead));
     const size_t off_img = ctl_region(1);
-    const int G = fwd_team_target(H, W);
+    const int G = fwd_single_team(H, W);
     const sc::Img d = make_fwd_img(src, img, H, W, C, pitch, target_w, seams_out, costs_out,
                                    base + off_img + sc::align_up(sizeof(sc::Img), sc::kAlign), ctl, G);
     // header (magic, one image) and the descriptor, which the kernels read from the workspace
