@@ -44,3 +44,25 @@ def test_candidates_are_known_variants():
     # variant ids the tuner tries must exist in the library's variant table (10 compiled variants)
     for v, g in tune.BATCH_CANDIDATES + tune.SINGLE_CANDIDATES:
         assert 0 <= v < 10 and 1 <= g <= 32
+
+
+def test_packaged_cache_is_consistent():
+    """The cache shipped in the package: every entry names a compiled variant and a team the
+    library accepts, records its fastest candidate, and the keys cover the benchmarked shapes
+    (the 256-image batch, 1920x1080 and 3840x2160 single images)."""
+    import json
+    import re
+
+    with open(tune.DEFAULT_CACHE) as f:
+        data = json.load(f)
+    assert data, "empty cache"
+    for key, e in data.items():
+        assert re.fullmatch(r"gfx\w+/(single/\d+x\d+|batch/\d+x\d+/n\d+)", key), key
+        assert 0 <= e["variant"] < 10 and 1 <= e["team"] <= 32, (key, e)
+        cands = {k: v for k, v in e.get("candidates", {}).items()}
+        if cands:
+            best = min(cands.values())
+            assert cands[f"v{e['variant']}/g{e['team']}"] == best == e["ms"], key
+    assert tune.key_single("gfx950", 1080, 1920) in data
+    assert tune.key_single("gfx950", 2160, 3840) in data
+    assert tune.key_batch("gfx950", [(2160, 2160)] * 256) in data
